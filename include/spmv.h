@@ -1,0 +1,229 @@
+/*
+ * spmv.h -- C-ABI of libspmv.so, an MI355X (gfx950) SpMV library over the
+ * five storage formats studied in arXiv 1805.11938 ("Optimizing Sparse
+ * Matrix-Vector Multiplication on Emerging Many-Core Architectures").
+ *
+ * The operation (Sec. II-A): y = A x, A sparse M x N, x and y dense.
+ * Formats (Sec. II-B, Table I): CSR, CSR5, ELL, SELL / SELL-C-sigma,
+ * HYB = ELL + COO.  Adaptive format selection from static matrix features
+ * (Sec. V): features, min-max scaling and a learned classifier.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Status codes, never exceptions; spmv_last_error() gives a message for
+ *   the calling thread's last failure.
+ * - Indices are int32 (M, N, nnz < 2^31); slot offsets inside padded
+ *   formats are int64.  Values are FP64 or FP32 (spmv_dtype_t); the
+ *   kernels accumulate in FP64 for both.
+ * - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *   Calls that only enqueue device work are asynchronous on that stream;
+ *   calls that return host data (features, select, to_csr/export to host,
+ *   timing) synchronise it.  Library-internal allocations use hipMalloc.
+ * - Matrix handles (spmv_mat_t) own their device arrays: creation copies
+ *   the caller's arrays, so the caller may free them afterwards.  Handles
+ *   are immutable after creation; concurrent runs on different streams
+ *   are safe.  x, y, X, Y stay owned by the caller: device pointers of the
+ *   handle's dtype.
+ * - y is overwritten (beta = 0).  x and y must not overlap.
+ */
+#ifndef SPMV_H
+#define SPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Format = class index of the selector (Sec. V-B, Table II column order). */
+typedef enum { SPMV_FMT_CSR = 0, SPMV_FMT_CSR5 = 1, SPMV_FMT_ELL = 2, SPMV_FMT_SELL = 3, SPMV_FMT_HYB = 4 } spmv_fmt_t;
+#define SPMV_NUM_FORMATS 5
+
+typedef enum { SPMV_F64 = 0, SPMV_F32 = 1 } spmv_dtype_t;
+
+typedef enum {
+  SPMV_OK = 0,
+  SPMV_ERR_INVALID_ARG = -1,   /* null handle/pointer, bad size, x == y, fmt mismatch */
+  SPMV_ERR_BAD_STRUCTURE = -2, /* malformed CSR/COO (ptr not monotone, col out of range, unsorted/duplicate col) */
+  SPMV_ERR_OOM = -3,           /* device allocation failed, or SPMV_MEM_CAP_BYTES exceeded */
+  SPMV_ERR_TOO_LARGE = -4,     /* padded format would exceed the byte cap (ELL / SELL / HYB) or int limits */
+  SPMV_ERR_UNSUPPORTED = -5,   /* parameter combination the kernels do not implement */
+  SPMV_ERR_HIP = -6,           /* a HIP runtime call failed */
+  SPMV_ERR_MODEL = -7          /* model file missing, corrupt, or of the wrong version */
+} spmv_status_t;
+
+typedef struct spmv_mat_s* spmv_mat_t;
+typedef struct spmv_model_s* spmv_model_t;
+typedef struct spmv_batch_s* spmv_batch_t;
+typedef void* spmv_stream_t; /* hipStream_t */
+
+/* Tuning parameters (Sec. II-B names omega, sigma for CSR5, C and sigma for
+ * SELL-C-sigma, and HYB's K).  Zero / -1 fields take the defaults below. */
+typedef struct {
+  int32_t sell_C;            /* chunk height C in {8,16,32,64}; default 32 */
+  int32_t sell_sigma;        /* sort window sigma >= 1 (1 = plain SELL); default 1 */
+  int32_t csr_lanes_per_row; /* 0 = nnz-balanced row blocks (default); V in {1,2,4,..,64} = V lanes per row */
+  int32_t hyb_K;             /* ELL width of HYB; -1 = the one-third rule (default) */
+  int32_t csr5_omega;        /* tile width; must divide 64 for spmv_run; default 64 */
+  int32_t csr5_sigma;        /* tile height 1..32; default 16 */
+  int64_t max_bytes;         /* byte cap of the converted format; 0 = default (SPMV_MAX_BYTES env or 64 GiB) */
+  uint32_t flags;            /* SPMV_FLAG_* */
+} spmv_params_t;
+
+#define SPMV_FLAG_NO_CHECK 1u /* skip the structural validation of spmv_mat_from_csr */
+
+typedef struct {
+  int32_t fmt, dtype;
+  int64_t M, N, nnz;
+  int64_t bytes_fmt;     /* bytes one spmv_run streams: format arrays incl. padding/metadata, x once, y once */
+  int64_t bytes_min;     /* compulsory CSR bytes nnz*(sv+4) + 4(M+1) + N*sv + M*sv (format independent) */
+  int64_t pad_slots;     /* stored slots that hold padding (ELL / SELL / HYB-ELL) */
+  int64_t aux;           /* HYB: COO entries; CSR5: tiles; SELL: chunks; CSR: row blocks */
+  spmv_params_t params;  /* the parameters the handle was built with (defaults resolved) */
+} spmv_info_t;
+
+const char* spmv_status_str(spmv_status_t st);
+const char* spmv_last_error(void);
+
+/* ------------------------------------------------------------ creation */
+
+/* CSR matrix from caller arrays (Sec. II-B, CSR): ptr[M+1] with ptr[0] = 0
+ * and ptr[M] = nnz, col[nnz] strictly increasing inside each row, val[nnz]
+ * of dtype dt.  src_on_device: 0 = host arrays, 1 = device arrays.  The
+ * structure is checked on the device unless SPMV_FLAG_NO_CHECK is passed in
+ * flags: BAD_STRUCTURE on failure.  Synchronises s. */
+spmv_status_t spmv_mat_from_csr(int64_t M, int64_t N, int64_t nnz, const int32_t* ptr, const int32_t* col,
+                                const void* val, spmv_dtype_t dt, int src_on_device, uint32_t flags,
+                                spmv_stream_t s, spmv_mat_t* out);
+
+/* CSR matrix from raw COO triplets (Sec. II-B, COO; Sec. III-D reads Matrix
+ * Market into COO before converting): on the device, the n triplets are
+ * stably sorted by (row, col), duplicates are summed left to right in input
+ * order, explicit zeros are kept.  Out-of-range coordinates -> BAD_STRUCTURE.
+ * Synchronises s. */
+spmv_status_t spmv_mat_from_coo(int64_t M, int64_t N, int64_t n, const int32_t* row, const int32_t* col,
+                                const void* val, spmv_dtype_t dt, int src_on_device, spmv_stream_t s,
+                                spmv_mat_t* out);
+
+/* Convert a CSR handle to fmt (Sec. II-B; Table I): a new handle.  p may be
+ * NULL (defaults).  ELL/SELL/HYB above the byte cap -> TOO_LARGE.
+ * Conversion runs on the device; it synchronises s (sizes come back). */
+spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* p, spmv_stream_t s,
+                           spmv_mat_t* out);
+
+/* Inverse conversion of any handle back to CSR arrays (bit-exact round
+ * trip).  dst_on_device: 0 = host buffers (synchronises s), 1 = device. */
+spmv_status_t spmv_to_csr(spmv_mat_t A, int32_t* ptr, int32_t* col, void* val, int dst_on_device, spmv_stream_t s);
+
+/* Copy a named internal array to host memory (golden tests).  Names:
+ * "ptr","col","val" (CSR; CSR5 keeps CSR's ptr); "ell_col","ell_val"
+ * (ELL and HYB, column-major M x K); "sell_perm","sell_cs","sell_col",
+ * "sell_val"; "coo_row","coo_col","coo_val" (HYB); "tile_ptr","bit_flag",
+ * "y_off","seg_off","tile_col","tile_val","tail_col","tail_val" (CSR5).
+ * spmv_array_bytes reports the size; export fails with INVALID_ARG when
+ * bytes is smaller.  Synchronises s. */
+spmv_status_t spmv_array_bytes(spmv_mat_t A, const char* name, size_t* bytes);
+spmv_status_t spmv_export(spmv_mat_t A, const char* name, void* dst, size_t bytes, spmv_stream_t s);
+
+spmv_status_t spmv_mat_info(spmv_mat_t A, spmv_info_t* info);
+void spmv_mat_free(spmv_mat_t A);
+
+/* ------------------------------------------------------------------ run */
+
+/* y = A x (Sec. II-A) with the kernel of A's format.  fmt must equal A's
+ * format (INVALID_ARG otherwise).  x: N values, y: M values, device memory,
+ * A's dtype. */
+spmv_status_t spmv_run(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, spmv_stream_t s);
+
+/* Y = A X for k right-hand sides, row-major: X[j*ldx + c], Y[i*ldy + c],
+ * c < k <= 64, ldx >= k, ldy >= k.  A must be CSR or SELL. */
+spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t k, spmv_stream_t s);
+
+/* Batched launch: n CSR handles of one dtype processed by one persistent
+ * kernel whose work list is balanced by nonzeros.  create builds the
+ * device work list; run takes host arrays of n device pointers. */
+spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* out);
+spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s);
+void spmv_batch_free(spmv_batch_t b);
+
+/* ---------------------------------------------------------- measurement */
+
+/* Timing in the manner of Sec. V-B: repeat until the 95% confidence
+ * interval of the mean is narrower than rel_ci (0.05 = the paper's 5%
+ * gap), with at least min_reps and at most max_reps launches, after
+ * `warmup` untimed ones.  Each launch is bracketed by HIP events on s;
+ * scrub_bytes > 0 runs a cache-scrub kernel over that many bytes before
+ * every launch, outside the events (cold L2 / Infinity Cache).
+ * out[0..4] = median ms, mean ms, CI half-width ms, reps, min ms. */
+spmv_status_t spmv_time(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, int warmup, int min_reps,
+                        int max_reps, double rel_ci, int64_t scrub_bytes, spmv_stream_t s, double out[5]);
+
+/* Enqueue the cache scrub on s (writes scrub_bytes of a library buffer). */
+spmv_status_t spmv_scrub(int64_t scrub_bytes, spmv_stream_t s);
+
+/* Device-to-device copy probe: returns the GB/s of a plain copy kernel
+ * reading and writing `bytes` each (median of reps). */
+spmv_status_t spmv_copy_probe(int64_t bytes, int reps, spmv_stream_t s, double* gbps);
+
+/* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: V;
+ * HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma) on x/y and write the
+ * fastest into *inout.  ms_out (optional) receives the best median. */
+spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void* y, int64_t scrub_bytes, int reps,
+                            spmv_params_t* inout, double* ms_out, spmv_stream_t s);
+
+/* ------------------------------------------------------------ selection */
+
+/* The 12 static features of A (Sec. V-B, Table IV, plus nnz, ELL padding
+ * ratio, bandwidth and Gini of row lengths), in FP64:
+ * n_rows, n_cols, nnz, nnz_frac, nnz_min, nnz_max, nnz_avg, nnz_std,
+ * variation (= std/avg), ell_pad (= M*max/nnz), bandwidth (max |i-j|),
+ * gini.  Computed on the device; A must be CSR.  Synchronises s. */
+spmv_status_t spmv_features(spmv_mat_t A, double out[12], spmv_stream_t s);
+
+/* MLP selector, 12 -> 64 -> 64 -> 5, FP32, ReLU (Sec. V-D lists an MLP
+ * among the classifiers).  Parameter vector (5317 floats): W1[12x64],
+ * b1[64], W2[64x64], b2[64], W3[64x5], b3[5], W row-major (fan_in, fan_out).
+ * A model also holds the feature scaler (per-feature min and max of the
+ * training set after the log transform, Sec. V-B "Feature Scaling"). */
+#define SPMV_MLP_NPARAM 5317
+spmv_status_t spmv_model_create(const float* params, const double fmin[12], const double fmax[12],
+                                spmv_model_t* out);
+spmv_status_t spmv_model_load(const char* path, spmv_model_t* out);
+spmv_status_t spmv_model_save(spmv_model_t m, const char* path);
+spmv_status_t spmv_model_params(spmv_model_t m, float* params_out, double fmin[12], double fmax[12]);
+void spmv_model_free(spmv_model_t m);
+
+/* Predict the format for raw features (Sec. V-A: features -> scaled ->
+ * model -> label): transform + scaling + forward + argmax on the device.
+ * scores (optional) receives the 5 logits.  Ties go to the lower index. */
+spmv_status_t spmv_select(spmv_model_t m, const double features[12], spmv_fmt_t* best, float scores[5]);
+
+/* Training kernels, exported for gradient checks.  All pointers are device
+ * memory, FP32.  X: B x 12 scaled features (row-major); params: 5317.
+ * forward: Z (B x 5 logits), A1/A2 (B x 64 pre-activations, may be NULL).
+ * backward: labels[B] int32 in 0..4; grads (5317) = d(mean CE)/d(params);
+ * loss (1 float, optional).  adam: one step t >= 1 on params with moments
+ * m, v (5317 each). */
+spmv_status_t spmv_mlp_forward(const float* params, const float* X, int32_t B, float* Z, float* A1, float* A2,
+                               spmv_stream_t s);
+spmv_status_t spmv_mlp_backward(const float* params, const float* X, const int32_t* labels, int32_t B,
+                                float* grads, float* loss, spmv_stream_t s);
+spmv_status_t spmv_mlp_adam(float* params, const float* grads, float* m, float* v, int32_t t, float lr, float beta1,
+                            float beta2, float eps, spmv_stream_t s);
+/* Feature transform + min-max scaling on the device: F (n x 12 FP64 raw
+ * features) -> X (n x 12 FP32 scaled).  fmin/fmax: host arrays. */
+spmv_status_t spmv_scale_features(const double* F, int32_t n, const double fmin[12], const double fmax[12],
+                                  float* X, spmv_stream_t s);
+/* Whole training run: epochs x (n / batch) Adam steps over device data X
+ * (n x 12 scaled), labels (n); order (epochs x n int32, device) gives the
+ * sample order of every epoch; the last partial batch is used as is.
+ * params (device, 5317) are trained in place; loss_out (host, epochs,
+ * optional) receives each epoch's mean training loss.  Synchronises s. */
+spmv_status_t spmv_mlp_train(float* params, const float* X, const int32_t* labels, int32_t n, const int32_t* order,
+                             int32_t epochs, int32_t batch, float lr, spmv_stream_t s, float* loss_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMV_H */

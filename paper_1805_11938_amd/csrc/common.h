@@ -1,0 +1,238 @@
+// Internal declarations of libspmv (gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "spmv.h"
+
+namespace spmv {
+
+constexpr int BS = 256;    // threads per workgroup for the streaming kernels (4 wave64s)
+constexpr int WAVE = 64;
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+spmv_status_t fail(spmv_status_t st, const char* fmt, ...);
+
+#define SPMV_HIP(expr)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return ::spmv::fail(SPMV_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),  \
+                          __FILE__, __LINE__);                                                  \
+  } while (0)
+
+#define SPMV_TRY(expr)                   \
+  do {                                   \
+    spmv_status_t st_ = (expr);          \
+    if (st_ != SPMV_OK) return st_;      \
+  } while (0)
+
+#define SPMV_LAUNCH_CHECK() SPMV_HIP(hipGetLastError())
+
+// --------------------------------------------------------------- memory
+// Device allocations go through these so that SPMV_MEM_CAP_BYTES can cap
+// the library's live device memory (OOM is then reported, never a fault).
+spmv_status_t dmalloc(void** p, size_t bytes);
+void dfree(void* p);
+
+// A scoped device buffer for temporaries inside conversions.  Its release
+// waits for the device first, so no queued kernel can still be using it.
+struct DTmp {
+  void* p = nullptr;
+  ~DTmp() {
+    if (p) {
+      (void)hipDeviceSynchronize();
+      dfree(p);
+    }
+  }
+  spmv_status_t alloc(size_t bytes) { return dmalloc(&p, bytes); }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+inline hipStream_t hs(spmv_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int value_size(spmv_dtype_t dt) { return dt == SPMV_F64 ? 8 : 4; }
+int64_t default_max_bytes();
+
+}  // namespace spmv
+
+struct spmv_mat_s {
+  spmv_fmt_t fmt = SPMV_FMT_CSR;
+  spmv_dtype_t dt = SPMV_F64;
+  int64_t M = 0, N = 0, nnz = 0;
+  spmv_params_t params{};
+  int sv = 8;
+  std::vector<void*> owned;  // freed by spmv_mat_free
+
+  // CSR arrays (CSR; CSR5 keeps ptr and stores col/val tile-transposed)
+  int32_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  int32_t* blk_row = nullptr;  // CSR row blocks: block b owns rows [blk_row[b], blk_row[b+1])
+  int64_t nblk = 0;
+
+  // ELL, and the ELL part of HYB: column-major M x K, slot (i,k) at k*M + i
+  int64_t K = 0;
+  int32_t* ecol = nullptr;
+  void* eval = nullptr;
+
+  // SELL-C-sigma
+  int32_t C = 0, sigma = 1;
+  int64_t nchunks = 0, nslots = 0, Mpad = 0;
+  int32_t* perm = nullptr;  // Mpad entries (nullptr when sigma == 1)
+  int64_t* cs = nullptr;    // nchunks + 1 slot offsets
+  int32_t* scol = nullptr;
+  void* sval = nullptr;
+
+  // HYB COO part (row-major) and its row-aligned block boundaries
+  int64_t ncoo = 0, ncoo_blk = 0;
+  int32_t* crow = nullptr;
+  int32_t* ccol = nullptr;
+  void* cval = nullptr;
+  int32_t* coo_blk = nullptr;
+
+  // CSR5
+  int32_t omega = 0, c5sigma = 0;
+  int64_t ntiles = 0;
+  int32_t* tile_ptr = nullptr;   // ntiles + 1 (last = M)
+  uint32_t* bit_flag = nullptr;  // ntiles * omega packed words
+  int32_t* y_off = nullptr;
+  int32_t* seg_off = nullptr;
+  int32_t* tile_row = nullptr;   // ntiles + 1: tile_ptr[0..T-1] and the row holding the first tail entry
+  int32_t tail_rlo = 0;          // first row r with ptr[r] >= T*omega*sigma
+  int32_t c5_tail_row = 0;       // row holding the first tail entry (M when there is no tail)
+  int has_empty = 0;
+  int32_t* nzrow = nullptr;      // non-empty rows, ascending (only when has_empty)
+  int32_t* tile_nzbase = nullptr;
+  int64_t nchains = 0;
+  int32_t* chains = nullptr;     // (row, t_begin, t_end) triples for the carry fix-up
+  double* carry = nullptr;       // ntiles + 1 partial sums (run scratch)
+
+  int64_t bytes_fmt = 0, pad_slots = 0;
+
+  void* own(void* p) {
+    if (p) owned.push_back(p);
+    return p;
+  }
+};
+
+struct spmv_model_s {
+  float* d_params = nullptr;  // device, SPMV_MLP_NPARAM
+  double fmin[12], fmax[12];
+  float h_params[SPMV_MLP_NPARAM];
+};
+
+namespace spmv {
+
+// ----------------------------------------------------------- primitives
+// Exclusive scan of n inputs into out[0..n]; out[n] is the total.
+spmv_status_t scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+spmv_status_t scan_i64_to_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+spmv_status_t scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on the low key_bits bits.
+// On return *keys / *vals point at whichever buffer holds the result (the
+// input buffers or the given alternates).
+spmv_status_t radix_sort_pairs(uint64_t** keys, uint32_t** vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                               int key_bits, hipStream_t s);
+spmv_status_t device_max_i32(const int32_t* ptr_lens_src, int64_t M, int lens_from_ptr, int32_t* out_host,
+                             hipStream_t s);
+spmv_status_t copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t s);
+spmv_status_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------- builders
+spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s);
+spmv_status_t convert_ell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
+spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
+spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
+spmv_status_t convert_csr5(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
+spmv_status_t to_csr_device(spmv_mat_s* A, int32_t* ptr, int32_t* col, void* val, hipStream_t s);
+
+// ---------------------------------------------------------------- kernels
+spmv_status_t run_csr(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t run_ell(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t run_sell(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t run_hyb(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t run_csr5(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s);
+spmv_status_t dispatch_run(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+
+spmv_status_t mat_alloc(spmv_mat_s* A, void** p, size_t bytes);
+void resolve_params(const spmv_params_t* in, spmv_params_t* out);
+int64_t bytes_min(const spmv_mat_s* A);
+
+}  // namespace spmv
+
+// ------------------------------------------------------ device helpers
+#ifdef __HIPCC__
+namespace spmv {
+
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+
+// Sum over aligned groups of G lanes (G a power of two <= 64).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double group_sum_rt(double v, int G) {
+  for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// MI355X dispatches workgroups round-robin over its 8 XCDs (each with its
+// own L2).  This bijection gives each XCD a contiguous range of logical
+// blocks, so neighbouring row blocks (which share x) share an L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t n) {
+  const uint32_t q = n >> 3, r = n & 7u, x = bid & 7u, loc = bid >> 3;
+  return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+}
+
+// Sum of a 256-thread block (called by all threads; result valid in all).
+__device__ __forceinline__ double block_sum(double v, double* sh /* >= 4 doubles of LDS */) {
+  v = group_sum<64>(v);
+  __syncthreads();
+  if (__lane_id() == 0) sh[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+
+// sum of val[k] * x[col[k]] over k = a + first, a + first + stride, ... < e
+// (two independent accumulators, non-temporal loads of the matrix streams)
+template <typename T>
+__device__ __forceinline__ double row_dot(const int32_t* __restrict__ col, const T* __restrict__ val,
+                                          const T* __restrict__ x, int64_t a, int64_t e, int first, int stride) {
+  double s0 = 0.0, s1 = 0.0;
+  int64_t k = a + first;
+  for (; k + stride < e; k += 2 * stride) {
+    const int32_t c0 = ldnt(col + k), c1 = ldnt(col + k + stride);
+    const T v0 = ldnt(val + k), v1 = ldnt(val + k + stride);
+    s0 += (double)v0 * (double)x[c0];
+    s1 += (double)v1 * (double)x[c1];
+  }
+  if (k < e) s0 += (double)ldnt(val + k) * (double)x[ldnt(col + k)];
+  return s0 + s1;
+}
+
+}  // namespace spmv
+#endif

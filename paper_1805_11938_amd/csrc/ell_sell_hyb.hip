@@ -1,0 +1,656 @@
+// ELL, SELL-C-sigma and HYB (Sec. II-B; Table I): device conversions from
+// CSR, their inverses, and the SpMV kernels.
+//
+// ELL: M x K, K = longest row, column-major (slot (i,k) at k*M + i) so a
+//   wave's 64 rows read 64 consecutive slots per k; padding (-1, +0.0) is
+//   skipped by predicate and never reads x.  One thread per row.
+// SELL-C-sigma: strips of C rows, each its own ELL of width w_c, column-
+//   major inside the strip (slot (p,k) at cs[c] + k*C + p); rows sorted by
+//   descending length, stably, inside windows of sigma rows (perm maps a
+//   stored position to its row; y is written through it).  One thread per
+//   stored position.
+// HYB: ELL(K) + COO tail.  K from the one-third rule unless given.  The ELL
+//   kernel writes y, then the COO kernel adds the tail: COO entries are cut
+//   into blocks whose boundaries fall on row starts, so every row of the
+//   tail is finished by one workgroup (segmented reduction in LDS, carries
+//   between sub-chunks kept in the workgroup), without atomics.
+#include "common.h"
+
+namespace spmv {
+
+static unsigned grid_rows(int64_t n) {
+  int64_t g = cdiv(n, BS);
+  if (g < 1) g = 1;
+  if (g > (1 << 20)) g = 1 << 20;
+  return (unsigned)g;
+}
+
+static int bits_for(uint64_t v) {
+  int b = 0;
+  while (b < 64 && (v >> b)) ++b;
+  return b;
+}
+
+// ================================================================== ELL
+template <typename T>
+__global__ void k_csr_to_ell(int64_t M, int64_t K, const int32_t* ptr, const int32_t* col, const T* val, int32_t* ecol,
+                             T* eval) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ptr[i], len = ptr[i + 1] - a;
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t q = k * M + i;
+      if (k < len) {
+        ecol[q] = col[a + k];
+        eval[q] = val[a + k];
+      } else {
+        ecol[q] = -1;
+        eval[q] = (T)0;
+      }
+    }
+  }
+}
+
+// entries of row i kept in the ELL part: the first min(len, K)
+__global__ void k_ell_count(int64_t M, int64_t K, const int32_t* ecol, int32_t* len) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = 0;
+    while (k < K && ecol[k * M + i] >= 0) ++k;
+    len[i] = (int32_t)k;
+  }
+}
+
+// copies the ell_len[i] (<= K) ELL entries of row i to ptr[i] onward
+template <typename T>
+__global__ void k_ell_to_csr(int64_t M, const int32_t* ecol, const T* eval, const int32_t* ell_len, const int32_t* ptr,
+                             int32_t* col, T* val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ptr[i], len = ell_len[i];
+    for (int64_t k = 0; k < len; ++k) {
+      col[a + k] = ecol[k * M + i];
+      val[a + k] = eval[k * M + i];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_ell(int64_t M, int64_t K, const int32_t* __restrict__ ecol,
+                                            const T* __restrict__ eval, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= M) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t k = 0;
+  for (; k + 3 < K; k += 4) {
+    const int64_t q = k * M + i;
+    const int32_t c0 = ldnt(ecol + q), c1 = ldnt(ecol + q + M), c2 = ldnt(ecol + q + 2 * M), c3 = ldnt(ecol + q + 3 * M);
+    const T v0 = ldnt(eval + q), v1 = ldnt(eval + q + M), v2 = ldnt(eval + q + 2 * M), v3 = ldnt(eval + q + 3 * M);
+    if (c0 >= 0) s0 += (double)v0 * (double)x[c0];
+    if (c1 >= 0) s1 += (double)v1 * (double)x[c1];
+    if (c2 >= 0) s2 += (double)v2 * (double)x[c2];
+    if (c3 >= 0) s3 += (double)v3 * (double)x[c3];
+  }
+  for (; k < K; ++k) {
+    const int64_t q = k * M + i;
+    const int32_t c = ldnt(ecol + q);
+    const T v = ldnt(eval + q);
+    if (c >= 0) s0 += (double)v * (double)x[c];
+  }
+  y[i] = (T)((s0 + s1) + (s2 + s3));
+}
+
+template <typename T>
+static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const void* eval, const void* x, void* y,
+                                hipStream_t s) {
+  if (M == 0) return SPMV_OK;
+  k_ell<T><<<(unsigned)cdiv(M, BS), BS, 0, s>>>(M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
+}
+
+spmv_status_t run_ell(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (A->dt == SPMV_F64) return launch_ell<double>(A->M, A->K, A->ecol, A->eval, x, y, s);
+  return launch_ell<float>(A->M, A->K, A->ecol, A->eval, x, y, s);
+}
+
+static spmv_status_t check_cap(const spmv_mat_s* A, int64_t bytes, const char* what) {
+  const int64_t cap = A->params.max_bytes > 0 ? A->params.max_bytes : default_max_bytes();
+  if (bytes > cap)
+    return fail(SPMV_ERR_TOO_LARGE, "%s needs %lld bytes, above the cap of %lld", what, (long long)bytes,
+                (long long)cap);
+  return SPMV_OK;
+}
+
+static spmv_status_t build_ell_part(spmv_mat_s* src, spmv_mat_s* A, int64_t K, hipStream_t s) {
+  const int64_t M = src->M;
+  A->K = K;
+  SPMV_TRY(mat_alloc(A, (void**)&A->ecol, sizeof(int32_t) * M * K));
+  SPMV_TRY(mat_alloc(A, &A->eval, (size_t)A->sv * M * K));
+  if (M && K) {
+    if (A->dt == SPMV_F64)
+      k_csr_to_ell<double><<<grid_rows(M), BS, 0, s>>>(M, K, src->ptr, src->col, (const double*)src->val, A->ecol,
+                                                       (double*)A->eval);
+    else
+      k_csr_to_ell<float><<<grid_rows(M), BS, 0, s>>>(M, K, src->ptr, src->col, (const float*)src->val, A->ecol,
+                                                      (float*)A->eval);
+    SPMV_LAUNCH_CHECK();
+  }
+  return SPMV_OK;
+}
+
+spmv_status_t convert_ell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
+  int32_t K = 0;
+  SPMV_TRY(device_max_i32(src->ptr, src->M, 1, &K, s));
+  const int64_t slots = src->M * (int64_t)K;
+  SPMV_TRY(check_cap(A, slots * (4 + A->sv), "ELL"));
+  SPMV_TRY(build_ell_part(src, A, K, s));
+  A->pad_slots = slots - src->nnz;
+  A->bytes_fmt = slots * (4 + A->sv) + A->N * A->sv + A->M * A->sv;
+  return SPMV_OK;
+}
+
+// ============================================================ SELL-C-sigma
+__global__ void k_sell_keys(int64_t M, const int32_t* ptr, int64_t sigma, int64_t maxlen, uint64_t* key,
+                            uint32_t* idx) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t len = ptr[i + 1] - ptr[i];
+    key[i] = (uint64_t)(i / sigma) * (uint64_t)(maxlen + 1) + (uint64_t)(maxlen - len);
+    idx[i] = (uint32_t)i;
+  }
+}
+
+__global__ void k_sell_perm(int64_t M, int64_t Mpad, const uint32_t* sorted, int32_t* perm) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < Mpad; p += (int64_t)gridDim.x * blockDim.x)
+    perm[p] = p < M ? (int32_t)sorted[p] : -1;
+}
+
+__global__ void k_sell_width(int64_t M, int64_t nch, int C, const int32_t* ptr, const int32_t* perm, int64_t* cw) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t w = 0;
+    for (int p = 0; p < C; ++p) {
+      const int64_t pos = c * C + p;
+      const int64_t r = perm ? perm[pos] : (pos < M ? pos : -1);
+      if (r >= 0) {
+        const int64_t len = ptr[r + 1] - ptr[r];
+        w = len > w ? len : w;
+      }
+    }
+    cw[c] = w * C;
+  }
+}
+
+template <typename T>
+__global__ void k_csr_to_sell(int64_t M, int64_t Mpad, int C, const int32_t* ptr, const int32_t* col, const T* val,
+                              const int32_t* perm, const int64_t* cs, int32_t* scol, T* sval) {
+  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < Mpad;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = pos / C, p = pos % C;
+    const int64_t r = perm ? perm[pos] : (pos < M ? pos : -1);
+    const int64_t a = r >= 0 ? ptr[r] : 0, len = r >= 0 ? ptr[r + 1] - a : 0;
+    const int64_t base = cs[c], w = (cs[c + 1] - base) / C;
+    for (int64_t k = 0; k < w; ++k) {
+      const int64_t q = base + k * C + p;
+      if (k < len) {
+        scol[q] = col[a + k];
+        sval[q] = val[a + k];
+      } else {
+        scol[q] = -1;
+        sval[q] = (T)0;
+      }
+    }
+  }
+}
+
+__global__ void k_sell_count(int64_t M, int64_t Mpad, int C, const int32_t* perm, const int64_t* cs,
+                             const int32_t* scol, int32_t* len) {
+  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < Mpad;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = perm ? perm[pos] : (pos < M ? pos : -1);
+    if (r < 0) continue;
+    const int64_t c = pos / C, p = pos % C, base = cs[c], w = (cs[c + 1] - base) / C;
+    int64_t k = 0;
+    while (k < w && scol[base + k * C + p] >= 0) ++k;
+    len[r] = (int32_t)k;
+  }
+}
+
+template <typename T>
+__global__ void k_sell_to_csr(int64_t M, int64_t Mpad, int C, const int32_t* perm, const int64_t* cs,
+                              const int32_t* scol, const T* sval, const int32_t* ptr, int32_t* col, T* val) {
+  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < Mpad;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = perm ? perm[pos] : (pos < M ? pos : -1);
+    if (r < 0) continue;
+    const int64_t c = pos / C, p = pos % C, base = cs[c];
+    const int64_t a = ptr[r], len = ptr[r + 1] - a;
+    for (int64_t k = 0; k < len; ++k) {
+      col[a + k] = scol[base + k * C + p];
+      val[a + k] = sval[base + k * C + p];
+    }
+  }
+}
+
+template <typename T, int LOGC, bool PERM>
+__global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t Mpad, const int64_t* __restrict__ cs,
+                                             const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
+                                             const T* __restrict__ sval, const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int C = 1 << LOGC;
+  const int64_t pos = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (pos >= Mpad) return;
+  const int64_t c = pos >> LOGC;
+  const int p = (int)(pos & (C - 1));
+  const int64_t base = cs[c];
+  const int64_t w = (cs[c + 1] - base) >> LOGC;
+  const int32_t* cc = scol + base + p;
+  const T* vv = sval + base + p;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t k = 0;
+  for (; k + 1 < w; k += 2) {
+    const int32_t c0 = ldnt(cc + k * C), c1 = ldnt(cc + (k + 1) * C);
+    const T v0 = ldnt(vv + k * C), v1 = ldnt(vv + (k + 1) * C);
+    if (c0 >= 0) s0 += (double)v0 * (double)x[c0];
+    if (c1 >= 0) s1 += (double)v1 * (double)x[c1];
+  }
+  if (k < w) {
+    const int32_t c0 = ldnt(cc + k * C);
+    const T v0 = ldnt(vv + k * C);
+    if (c0 >= 0) s0 += (double)v0 * (double)x[c0];
+  }
+  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+  if (r >= 0) y[r] = (T)(s0 + s1);
+}
+
+template <typename T, int LOGC>
+static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  const unsigned g = (unsigned)cdiv(A->Mpad, BS);
+  if (A->perm)
+    k_sell<T, LOGC, true><<<g, BS, 0, s>>>(A->M, A->Mpad, A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x,
+                                           (T*)y);
+  else
+    k_sell<T, LOGC, false><<<g, BS, 0, s>>>(A->M, A->Mpad, A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x,
+                                            (T*)y);
+}
+
+template <typename T>
+static spmv_status_t run_sell_t(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (A->M == 0) return SPMV_OK;
+  switch (A->C) {
+    case 1: launch_sell_c<T, 0>(A, x, y, s); break;
+    case 2: launch_sell_c<T, 1>(A, x, y, s); break;
+    case 4: launch_sell_c<T, 2>(A, x, y, s); break;
+    case 8: launch_sell_c<T, 3>(A, x, y, s); break;
+    case 16: launch_sell_c<T, 4>(A, x, y, s); break;
+    case 32: launch_sell_c<T, 5>(A, x, y, s); break;
+    case 64: launch_sell_c<T, 6>(A, x, y, s); break;
+    default: return fail(SPMV_ERR_UNSUPPORTED, "SELL chunk C=%d (need a power of two <= 64)", A->C);
+  }
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
+}
+
+spmv_status_t run_sell(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (A->dt == SPMV_F64) return run_sell_t<double>(A, x, y, s);
+  return run_sell_t<float>(A, x, y, s);
+}
+
+spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
+  const int64_t M = src->M;
+  const int C = A->params.sell_C;
+  const int64_t sigma = A->params.sell_sigma;
+  if (C < 1 || C > 64 || (C & (C - 1))) return fail(SPMV_ERR_UNSUPPORTED, "SELL C=%d (need a power of two <= 64)", C);
+  if (sigma < 1) return fail(SPMV_ERR_INVALID_ARG, "SELL sigma=%lld", (long long)sigma);
+  A->C = C;
+  A->sigma = (int32_t)sigma;
+  A->nchunks = cdiv(M, C);
+  A->Mpad = A->nchunks * C;
+  const unsigned g = grid_rows(std::max<int64_t>(M, A->Mpad));
+  if (sigma > 1 && M > 0) {
+    int32_t maxlen = 0;
+    SPMV_TRY(device_max_i32(src->ptr, M, 1, &maxlen, s));
+    DTmp k1, k2, v1, v2;
+    SPMV_TRY(k1.alloc(sizeof(uint64_t) * M));
+    SPMV_TRY(k2.alloc(sizeof(uint64_t) * M));
+    SPMV_TRY(v1.alloc(sizeof(uint32_t) * M));
+    SPMV_TRY(v2.alloc(sizeof(uint32_t) * M));
+    uint64_t* keys = k1.as<uint64_t>();
+    uint32_t* idx = v1.as<uint32_t>();
+    k_sell_keys<<<g, BS, 0, s>>>(M, src->ptr, sigma, maxlen, keys, idx);
+    SPMV_LAUNCH_CHECK();
+    const uint64_t nwin = (uint64_t)cdiv(M, sigma);
+    SPMV_TRY(radix_sort_pairs(&keys, &idx, k2.as<uint64_t>(), v2.as<uint32_t>(), M,
+                              bits_for(nwin * (uint64_t)(maxlen + 1) - 1), s));
+    SPMV_TRY(mat_alloc(A, (void**)&A->perm, sizeof(int32_t) * A->Mpad));
+    k_sell_perm<<<g, BS, 0, s>>>(M, A->Mpad, idx, A->perm);
+    SPMV_LAUNCH_CHECK();
+    SPMV_HIP(hipStreamSynchronize(s));  // k1/k2/v1/v2 are freed on return
+  }
+  DTmp cw;
+  SPMV_TRY(cw.alloc(sizeof(int64_t) * std::max<int64_t>(A->nchunks, 1)));
+  SPMV_TRY(mat_alloc(A, (void**)&A->cs, sizeof(int64_t) * (A->nchunks + 1)));
+  if (A->nchunks) {
+    k_sell_width<<<grid_rows(A->nchunks), BS, 0, s>>>(M, A->nchunks, C, src->ptr, A->perm, cw.as<int64_t>());
+    SPMV_LAUNCH_CHECK();
+  }
+  SPMV_TRY(scan_i64_to_i64(cw.as<int64_t>(), A->cs, A->nchunks, s));
+  SPMV_TRY(copy_to_host(&A->nslots, A->cs + A->nchunks, sizeof(int64_t), s));
+  SPMV_TRY(check_cap(A, A->nslots * (4 + A->sv), "SELL"));
+  SPMV_TRY(mat_alloc(A, (void**)&A->scol, sizeof(int32_t) * A->nslots));
+  SPMV_TRY(mat_alloc(A, &A->sval, (size_t)A->sv * A->nslots));
+  if (A->Mpad) {
+    if (A->dt == SPMV_F64)
+      k_csr_to_sell<double><<<g, BS, 0, s>>>(M, A->Mpad, C, src->ptr, src->col, (const double*)src->val, A->perm, A->cs,
+                                             A->scol, (double*)A->sval);
+    else
+      k_csr_to_sell<float><<<g, BS, 0, s>>>(M, A->Mpad, C, src->ptr, src->col, (const float*)src->val, A->perm, A->cs,
+                                            A->scol, (float*)A->sval);
+    SPMV_LAUNCH_CHECK();
+  }
+  A->pad_slots = A->nslots - src->nnz;
+  A->bytes_fmt = A->nslots * (4 + A->sv) + (A->nchunks + 1) * 8 + (A->perm ? A->Mpad * 4 : 0) + A->N * A->sv +
+                 A->M * A->sv;
+  SPMV_HIP(hipStreamSynchronize(s));
+  return SPMV_OK;
+}
+
+// ================================================================== HYB
+constexpr int COO_CH = 2048;  // entries per COO sub-chunk (LDS)
+constexpr int COO_IT = COO_CH / BS;
+
+__global__ void k_hyb_keys(int64_t M, const int32_t* ptr, int64_t maxlen, uint64_t* key, uint32_t* idx) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    key[i] = (uint64_t)(maxlen - (ptr[i + 1] - ptr[i]));
+    idx[i] = (uint32_t)i;
+  }
+}
+
+__global__ void k_hyb_tail_count(int64_t M, int64_t K, const int32_t* ptr, int32_t* tcnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t len = ptr[i + 1] - ptr[i];
+    tcnt[i] = (int32_t)(len > K ? len - K : 0);
+  }
+}
+
+// one wave per row copies the row's entries beyond K into the COO arrays
+template <typename T>
+__global__ void k_hyb_fill_coo(int64_t M, int64_t K, const int32_t* ptr, const int32_t* col, const T* val,
+                               const int64_t* off, int32_t* crow, int32_t* ccol, T* cval) {
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; i < M; i += nw) {
+    const int64_t a = ptr[i] + K, e = ptr[i + 1], o = off[i] - a;
+    for (int64_t k = a + __lane_id(); k < e; k += WAVE) {
+      crow[o + k] = (int32_t)i;
+      ccol[o + k] = col[k];
+      cval[o + k] = val[k];
+    }
+  }
+}
+
+// block b processes COO entries [blk[b], blk[b+1]); boundaries on row starts
+__global__ void k_coo_blocks(int64_t ncoo, int64_t nb, const int32_t* crow, int32_t* blk) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nb; b += (int64_t)gridDim.x * blockDim.x) {
+    int64_t s = b * COO_CH;
+    if (b == 0) s = 0;
+    else if (b == nb || s >= ncoo) s = ncoo;
+    else if (crow[s] == crow[s - 1]) {
+      const int32_t r = crow[s];
+      int64_t lo = s, hi = ncoo;  // first entry after row r
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (crow[mid] > r) hi = mid;
+        else lo = mid + 1;
+      }
+      s = lo;
+    }
+    blk[b] = (int32_t)s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coo(const int32_t* __restrict__ blk, const int32_t* __restrict__ crow,
+                                            const int32_t* __restrict__ ccol, const T* __restrict__ cval,
+                                            const T* __restrict__ x, T* __restrict__ y) {
+  __shared__ double prod[COO_CH];
+  __shared__ int32_t hpos[COO_CH + 1];
+  __shared__ int32_t wcnt[COO_IT * (BS / WAVE)];
+  __shared__ double carry_v;
+  __shared__ int32_t carry_r;
+  const int t = threadIdx.x, w = t / WAVE;
+  const int64_t s0 = blk[blockIdx.x], e0 = blk[blockIdx.x + 1];
+  if (s0 >= e0) return;
+  if (t == 0) carry_r = -1;
+  const uint64_t lt = lanemask_lt();
+  for (int64_t c0 = s0; c0 < e0; c0 += COO_CH) {
+    const int n = (int)std::min<int64_t>(COO_CH, e0 - c0);
+    const bool last_chunk = c0 + n >= e0;
+    int32_t cc[COO_IT];
+    T vv[COO_IT];
+    bool hd[COO_IT];
+    uint64_t mk[COO_IT];
+#pragma unroll
+    for (int j = 0; j < COO_IT; ++j) {
+      const int k = j * BS + t;
+      hd[j] = false;
+      if (k < n) {
+        cc[j] = ldnt(ccol + c0 + k);
+        vv[j] = ldnt(cval + c0 + k);
+        hd[j] = (k == 0) || (crow[c0 + k] != crow[c0 + k - 1]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < COO_IT; ++j) {
+      const int k = j * BS + t;
+      if (k < n) prod[k] = (double)vv[j] * (double)x[cc[j]];
+      mk[j] = __ballot(hd[j]);
+      if (__lane_id() == 0) wcnt[j * (BS / WAVE) + w] = __popcll(mk[j]);
+    }
+    __syncthreads();
+    // flush a carried row that ended exactly at the previous sub-chunk
+    if (t == 0 && carry_r >= 0 && crow[c0] != carry_r) {
+      y[carry_r] = (T)((double)y[carry_r] + carry_v);
+      carry_r = -1;
+    }
+    int nh = 0;
+#pragma unroll
+    for (int j = 0; j < COO_IT; ++j) {
+      int before = nh;
+      for (int q = 0; q < w; ++q) before += wcnt[j * (BS / WAVE) + q];
+      for (int q = 0; q < BS / WAVE; ++q) nh += wcnt[j * (BS / WAVE) + q];
+      if (hd[j]) hpos[before + __popcll(mk[j] & lt)] = j * BS + t;
+    }
+    if (t == 0) hpos[nh] = n;
+    __syncthreads();
+    const int V = n / nh >= 32 ? 16 : n / nh >= 8 ? 4 : 1;
+    const int g = t / V, lane = t % V, ng = BS / V;
+    double keep_v = 0.0;
+    int32_t keep_r = -1;
+    for (int q = g; q < nh; q += ng) {
+      const int a = hpos[q], e = hpos[q + 1];
+      double sum = 0.0;
+      for (int k = a + lane; k < e; k += V) sum += prod[k];
+      sum = group_sum_rt(sum, V);
+      if (lane == 0) {
+        const int32_t r = crow[c0 + a];
+        if (q == 0 && r == carry_r) sum += carry_v;
+        if (q == nh - 1 && !last_chunk) {
+          keep_v = sum;
+          keep_r = r;
+        } else {
+          y[r] = (T)((double)y[r] + sum);
+        }
+      }
+    }
+    __syncthreads();
+    if (keep_r >= 0) {  // exactly one lane holds the open last segment
+      carry_v = keep_v;
+      carry_r = keep_r;
+    } else if (t == 0 && last_chunk) {
+      carry_r = -1;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (A->M == 0) return SPMV_OK;
+  SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, s));
+  if (A->ncoo > 0) {
+    k_coo<T><<<(unsigned)A->ncoo_blk, BS, 0, s>>>(A->coo_blk, A->crow, A->ccol, (const T*)A->cval, (const T*)x, (T*)y);
+    SPMV_LAUNCH_CHECK();
+  }
+  return SPMV_OK;
+}
+
+spmv_status_t run_hyb(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (A->dt == SPMV_F64) return run_hyb_t<double>(A, x, y, s);
+  return run_hyb_t<float>(A, x, y, s);
+}
+
+// K = the ceil(M/3)-th largest row length: the largest k with at least
+// ceil(M/3) rows of length >= k.
+static spmv_status_t hyb_rule_k(spmv_mat_s* src, int64_t* K, hipStream_t s) {
+  const int64_t M = src->M;
+  *K = 0;
+  if (M == 0) return SPMV_OK;
+  int32_t maxlen = 0;
+  SPMV_TRY(device_max_i32(src->ptr, M, 1, &maxlen, s));
+  DTmp k1, k2, v1, v2;
+  SPMV_TRY(k1.alloc(sizeof(uint64_t) * M));
+  SPMV_TRY(k2.alloc(sizeof(uint64_t) * M));
+  SPMV_TRY(v1.alloc(sizeof(uint32_t) * M));
+  SPMV_TRY(v2.alloc(sizeof(uint32_t) * M));
+  uint64_t* keys = k1.as<uint64_t>();
+  uint32_t* idx = v1.as<uint32_t>();
+  k_hyb_keys<<<grid_rows(M), BS, 0, s>>>(M, src->ptr, maxlen, keys, idx);
+  SPMV_LAUNCH_CHECK();
+  SPMV_TRY(radix_sort_pairs(&keys, &idx, k2.as<uint64_t>(), v2.as<uint32_t>(), M, bits_for((uint64_t)maxlen), s));
+  const int64_t need = (M + 2) / 3;
+  uint64_t kk = 0;
+  SPMV_TRY(copy_to_host(&kk, keys + (need - 1), sizeof(uint64_t), s));
+  *K = (int64_t)maxlen - (int64_t)kk;
+  return SPMV_OK;
+}
+
+spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
+  const int64_t M = src->M;
+  int64_t K = A->params.hyb_K;
+  if (K < 0) SPMV_TRY(hyb_rule_k(src, &K, s));
+  A->params.hyb_K = (int32_t)K;
+  SPMV_TRY(check_cap(A, M * K * (4 + A->sv), "HYB-ELL"));
+  SPMV_TRY(build_ell_part(src, A, K, s));
+  DTmp tc, off;
+  SPMV_TRY(tc.alloc(sizeof(int32_t) * std::max<int64_t>(M, 1)));
+  SPMV_TRY(off.alloc(sizeof(int64_t) * (M + 1)));
+  if (M) {
+    k_hyb_tail_count<<<grid_rows(M), BS, 0, s>>>(M, K, src->ptr, tc.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+  }
+  SPMV_TRY(scan_i32_to_i64(tc.as<int32_t>(), off.as<int64_t>(), M, s));
+  SPMV_TRY(copy_to_host(&A->ncoo, off.as<int64_t>() + M, sizeof(int64_t), s));
+  SPMV_TRY(mat_alloc(A, (void**)&A->crow, sizeof(int32_t) * A->ncoo));
+  SPMV_TRY(mat_alloc(A, (void**)&A->ccol, sizeof(int32_t) * A->ncoo));
+  SPMV_TRY(mat_alloc(A, &A->cval, (size_t)A->sv * A->ncoo));
+  A->ncoo_blk = std::max<int64_t>(cdiv(A->ncoo, COO_CH), 1);
+  SPMV_TRY(mat_alloc(A, (void**)&A->coo_blk, sizeof(int32_t) * (A->ncoo_blk + 1)));
+  if (A->ncoo) {
+    const unsigned gw = (unsigned)std::min<int64_t>(cdiv(M, BS / WAVE), 1 << 20);
+    if (A->dt == SPMV_F64)
+      k_hyb_fill_coo<double><<<gw, BS, 0, s>>>(M, K, src->ptr, src->col, (const double*)src->val, off.as<int64_t>(),
+                                               A->crow, A->ccol, (double*)A->cval);
+    else
+      k_hyb_fill_coo<float><<<gw, BS, 0, s>>>(M, K, src->ptr, src->col, (const float*)src->val, off.as<int64_t>(),
+                                              A->crow, A->ccol, (float*)A->cval);
+    SPMV_LAUNCH_CHECK();
+  }
+  k_coo_blocks<<<grid_rows(A->ncoo_blk + 1), BS, 0, s>>>(A->ncoo, A->ncoo_blk, A->crow, A->coo_blk);
+  SPMV_LAUNCH_CHECK();
+  A->pad_slots = M * K - (src->nnz - A->ncoo);
+  // ELL slots, COO (row, col, val), x once, y written once and the tail rows re-read
+  A->bytes_fmt = M * K * (4 + A->sv) + A->ncoo * (8 + A->sv) + A->N * A->sv + A->M * A->sv;
+  SPMV_HIP(hipStreamSynchronize(s));
+  return SPMV_OK;
+}
+
+// ============================================================ inverses
+template <typename T>
+static spmv_status_t to_csr_t(spmv_mat_s* A, int32_t* ptr, int32_t* col, T* val, hipStream_t s);
+
+__global__ void k_hyb_len(int64_t M, const int32_t* ell_len, const int32_t* tail_cnt, int32_t* len) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
+    len[i] = ell_len[i] + tail_cnt[i];
+}
+
+__global__ void k_coo_rowcount(int64_t n, const int32_t* crow, int32_t* cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[crow[i]], 1);
+}
+
+// COO tail of row r goes after its ELL entries: position ptr[r] + ell_len[r] + (k - first tail entry of r)
+template <typename T>
+__global__ void k_coo_to_csr(int64_t n, const int32_t* crow, const int32_t* ccol, const T* cval, const int32_t* ptr,
+                             const int32_t* ell_len, const int64_t* toff, int32_t* col, T* val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = crow[i];
+    const int64_t d = (int64_t)ptr[r] + ell_len[r] + (i - toff[r]);
+    col[d] = ccol[i];
+    val[d] = cval[i];
+  }
+}
+
+template <typename T>
+static spmv_status_t to_csr_t(spmv_mat_s* A, int32_t* ptr, int32_t* col, T* val, hipStream_t s) {
+  const int64_t M = A->M;
+  const unsigned g = grid_rows(std::max<int64_t>(M, A->Mpad));
+  DTmp len;
+  SPMV_TRY(len.alloc(sizeof(int32_t) * std::max<int64_t>(M, 1)));
+  if (A->fmt == SPMV_FMT_ELL || A->fmt == SPMV_FMT_HYB) {
+    if (M) {
+      k_ell_count<<<g, BS, 0, s>>>(M, A->K, A->ecol, len.as<int32_t>());
+      SPMV_LAUNCH_CHECK();
+    }
+    if (A->fmt == SPMV_FMT_ELL || A->ncoo == 0) {
+      SPMV_TRY(scan_i32_to_i32(len.as<int32_t>(), ptr, M, s));
+      if (M) {
+        k_ell_to_csr<T><<<g, BS, 0, s>>>(M, A->ecol, (const T*)A->eval, len.as<int32_t>(), ptr, col, val);
+        SPMV_LAUNCH_CHECK();
+      }
+      return SPMV_OK;
+    }
+    DTmp cnt, tot, toff;
+    SPMV_TRY(cnt.alloc(sizeof(int32_t) * M));
+    SPMV_TRY(tot.alloc(sizeof(int32_t) * M));
+    SPMV_TRY(toff.alloc(sizeof(int64_t) * (M + 1)));
+    SPMV_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * M, s));
+    const unsigned gc = grid_rows(A->ncoo);
+    k_coo_rowcount<<<gc, BS, 0, s>>>(A->ncoo, A->crow, cnt.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+    SPMV_TRY(scan_i32_to_i64(cnt.as<int32_t>(), toff.as<int64_t>(), M, s));  // first COO entry of each row
+    k_hyb_len<<<g, BS, 0, s>>>(M, len.as<int32_t>(), cnt.as<int32_t>(), tot.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+    SPMV_TRY(scan_i32_to_i32(tot.as<int32_t>(), ptr, M, s));
+    k_ell_to_csr<T><<<g, BS, 0, s>>>(M, A->ecol, (const T*)A->eval, len.as<int32_t>(), ptr, col, val);
+    SPMV_LAUNCH_CHECK();
+    k_coo_to_csr<T><<<gc, BS, 0, s>>>(A->ncoo, A->crow, A->ccol, (const T*)A->cval, ptr, len.as<int32_t>(),
+                                      toff.as<int64_t>(), col, val);
+    SPMV_LAUNCH_CHECK();
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+  }
+  // SELL
+  if (A->Mpad) {
+    k_sell_count<<<g, BS, 0, s>>>(M, A->Mpad, A->C, A->perm, A->cs, A->scol, len.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+  }
+  SPMV_TRY(scan_i32_to_i32(len.as<int32_t>(), ptr, M, s));
+  if (A->Mpad) {
+    k_sell_to_csr<T><<<g, BS, 0, s>>>(M, A->Mpad, A->C, A->perm, A->cs, A->scol, (const T*)A->sval, ptr, col, val);
+    SPMV_LAUNCH_CHECK();
+  }
+  SPMV_HIP(hipStreamSynchronize(s));
+  return SPMV_OK;
+}
+
+spmv_status_t ell_sell_hyb_to_csr(spmv_mat_s* A, int32_t* ptr, int32_t* col, void* val, hipStream_t s) {
+  if (A->dt == SPMV_F64) return to_csr_t<double>(A, ptr, col, (double*)val, s);
+  return to_csr_t<float>(A, ptr, col, (float*)val, s);
+}
+
+}  // namespace spmv

@@ -1,0 +1,257 @@
+"""GPU parity: every format kernel and device conversion against the oracle,
+through the C-ABI.  Bit-exact for conversions and integer-valued inputs;
+max row-wise relative error 1e-12 (FP64) / 1e-5 (FP32) otherwise."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_11938_amd import synth
+from paper_1805_11938_amd import spmv as S
+
+from gpu_util import FORMAT_CONFIGS, TOL, as_dtype, device_vec, reference, rowwise_err
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the GPU"
+    return torch
+
+
+def table1_csr(dt=0):
+    g = GOLD["coo"]
+    return S.Matrix.from_coo(4, 4, g["row"], g["col"], np.array(g["data"], float), dt)
+
+
+# ------------------------------------------------------------- Table I
+
+def test_table1_device_conversions(torch):
+    A = table1_csr()
+    p, c, v = A.to_csr()
+    assert p.tolist() == GOLD["csr"]["ptr"] and c.tolist() == GOLD["csr"]["indices"]
+    assert v.tolist() == GOLD["csr"]["data"]
+    E = A.convert("ell")
+    ec = E.export("ell_col", np.int32).reshape(-1, 4).T  # column-major M x K
+    ev = E.export("ell_val", np.float64).reshape(-1, 4).T
+    assert [[None if c < 0 else int(c) for c in r] for r in ec] == GOLD["ell"]["indices"]
+    assert [[None if c < 0 else float(x) for c, x in zip(rc, rv)] for rc, rv in zip(ec, ev)] == GOLD["ell"]["data"]
+    for key in ("sell", "sell_c_sigma"):
+        g = GOLD[key]
+        Sm = A.convert("sell", sell_C=g["C"], sell_sigma=g["sigma"])
+        cs = Sm.export("sell_cs", np.int64)
+        assert (np.diff(cs) // g["C"]).tolist() == g["slices"]
+        sc = Sm.export("sell_col", np.int32)
+        rows = []
+        for ch in range(len(cs) - 1):
+            w = (cs[ch + 1] - cs[ch]) // g["C"]
+            for pp in range(g["C"]):
+                rows.append([None if sc[cs[ch] + k * g["C"] + pp] < 0 else int(sc[cs[ch] + k * g["C"] + pp])
+                             for k in range(w)])
+        assert rows == g["indices"]
+        if g["sigma"] > 1:
+            assert Sm.export("sell_perm", np.int32).tolist() == g["row_order"]
+    H = A.convert("hyb")
+    assert H.params["hyb_K"] == GOLD["hyb"]["K"]
+    assert H.export("coo_row", np.int32).tolist() == GOLD["hyb"]["coo"]["row"]
+    assert H.export("coo_col", np.int32).tolist() == GOLD["hyb"]["coo"]["col"]
+    assert H.export("coo_val", np.float64).tolist() == GOLD["hyb"]["coo"]["data"]
+    g = GOLD["csr5"]
+    C5 = A.convert("csr5", csr5_omega=2, csr5_sigma=2)
+    assert C5.export("tile_ptr", np.int32).tolist() == g["tile_ptr"]
+    fl = C5.export("bit_flag", np.uint32)
+    flags = [[bool((fl[t * 2 + l] >> i) & 1) for i in range(2) for l in range(2)] for t in range(2)]
+    assert flags == g["bit_flag"]
+    assert C5.export("y_off", np.int32).reshape(2, 2).tolist() == g["y_off"]
+    assert C5.export("seg_off", np.int32).reshape(2, 2).tolist() == g["seg_off"]
+    assert C5.export("tile_col", np.int32).reshape(2, 4).tolist() == g["indices"]
+    assert C5.export("tile_val", np.float64).reshape(2, 4).tolist() == g["data"]
+
+
+def test_table1_every_kernel(torch):
+    A = table1_csr()
+    x = torch.tensor([1.0, 2, 3, 4], dtype=torch.float64, device="cuda")
+    for fmt, kw in FORMAT_CONFIGS + [("csr5", {"csr5_omega": 2, "csr5_sigma": 2}), ("sell", {"sell_C": 2, "sell_sigma": 4})]:
+        B = A.convert(fmt, **kw)
+        assert B.run(x).cpu().tolist() == [15, 38, 12, 29], (fmt, kw)
+
+
+# ------------------------------------------------------- parity cases
+
+def cases():
+    out = [("laplace2d_64", synth.laplace2d(64))]
+    for seed, (M, N, d) in enumerate([(1, 1, 1.0), (7, 5, 0.4), (300, 200, 0.05), (2500, 2500, 0.004),
+                                      (1000, 3000, 0.01), (5000, 1, 0.3)]):
+        out.append((f"rand{M}x{N}", synth.random_pattern(M, N, d, 100 + seed, integer_values=(seed % 2 == 1))))
+    out.append(("zipf_20k", synth.zipf_rows(20_000, 20_000, 2.0, 16, 5_000, 4, 5)))
+    out.append(("uniform_empty", synth.uniform_random(30_000, 30_000, 1.5, 7, 8)))  # many empty rows
+    A = np.zeros((50, 9000))
+    A[3, :] = 1.0
+    A[40, ::2] = -2.0
+    out.append(("long_rows", synth.from_dense(A)))
+    out.append(("empty", synth.from_dense(np.zeros((70, 30)))))
+    out.append(("banded", synth.banded(40_000, 17, 0.6, 9, 10)))
+    out.append(("blockdiag", synth.blockdiag(20_000, 300, 0.2, 11, 12)))
+    return out
+
+
+CASES = cases()
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+@pytest.mark.parametrize("ci", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_formats_match_oracle(torch, ci, dt):
+    name, A = CASES[ci]
+    x64 = synth.vector(A.N, 1000 + ci)
+    if dt == 1:
+        x64 = x64.astype(np.float32).astype(np.float64)
+    integer = np.all(A.val == np.round(A.val))
+    if integer:
+        x64 = np.round(x64 * 8)
+    yref, den = reference(A, x64, dt)
+    Ad = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, as_dtype(A, dt), dt)
+    x = device_vec(x64, dt)
+    for fmt, kw in FORMAT_CONFIGS:
+        B = Ad.convert(fmt, **kw)
+        y = torch.full((A.M,), float("nan"), dtype=S.torch_dtype(dt), device="cuda")
+        B.run(x, y)
+        got = y.cpu().numpy().astype(np.float64)
+        if integer:
+            assert np.array_equal(got, yref), (name, fmt, kw)
+        else:
+            err = rowwise_err(got, yref, den)
+            assert err <= TOL[dt], (name, fmt, kw, err)
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_device_conversions_bit_identical(torch, ci):
+    name, A = CASES[ci]
+    Ad = S.Matrix.from_host(A)
+    M = A.M
+    # ELL
+    K, ec, ev = oracle.csr_to_ell(M, A.ptr, A.col, A.val)
+    E = Ad.convert("ell")
+    assert np.array_equal(E.export("ell_col", np.int32), ec)
+    assert np.array_equal(E.export("ell_val", np.float64).view(np.uint64), ev.view(np.uint64))
+    # SELL-C-sigma
+    for C, sg in [(32, 1), (8, 64), (64, 8192)]:
+        o = oracle.csr_to_sell(M, A.ptr, A.col, A.val, C, sg)
+        Sm = Ad.convert("sell", sell_C=C, sell_sigma=sg)
+        assert np.array_equal(Sm.export("sell_cs", np.int64), o["cs"])
+        assert np.array_equal(Sm.export("sell_col", np.int32), o["col"])
+        assert np.array_equal(Sm.export("sell_val", np.float64).view(np.uint64), o["val"].view(np.uint64))
+        if sg > 1 and M > 0:
+            assert np.array_equal(Sm.export("sell_perm", np.int32), o["perm"])
+    # HYB (rule and a fixed K)
+    for Kh in (None, 1):
+        o = oracle.csr_to_hyb(M, A.ptr, A.col, A.val, Kh)
+        H = Ad.convert("hyb", **({} if Kh is None else {"hyb_K": Kh}))
+        assert H.params["hyb_K"] == o["K"]
+        assert np.array_equal(H.export("ell_col", np.int32), o["ell_col"])
+        assert np.array_equal(H.export("coo_row", np.int32), o["coo_row"])
+        assert np.array_equal(H.export("coo_col", np.int32), o["coo_col"])
+        assert np.array_equal(H.export("coo_val", np.float64).view(np.uint64), o["coo_val"].view(np.uint64))
+    # CSR5
+    for w, s in [(64, 16), (32, 4), (2, 2)]:
+        o = oracle.csr_to_csr5(M, A.ptr, A.col, A.val, w, s)
+        C5 = Ad.convert("csr5", csr5_omega=w, csr5_sigma=s)
+        for nm, dt_ in [("tile_ptr", np.int32), ("bit_flag", np.uint32), ("y_off", np.int32), ("seg_off", np.int32)]:
+            assert np.array_equal(C5.export(nm, dt_), o[nm]), (name, nm)
+        assert np.array_equal(C5.export("tile_col", np.int32), o["col"])
+        assert np.array_equal(C5.export("tile_val", np.float64).view(np.uint64), o["val"].view(np.uint64))
+        assert np.array_equal(C5.export("tail_col", np.int32), o["tail_col"])
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_round_trips_bit_exact(torch, ci):
+    name, A = CASES[ci]
+    Ad = S.Matrix.from_host(A)
+    for fmt, kw in FORMAT_CONFIGS:
+        p, c, v = Ad.convert(fmt, **kw).to_csr()
+        assert np.array_equal(p, A.ptr), (fmt, kw)
+        assert np.array_equal(c, A.col), (fmt, kw)
+        assert np.array_equal(v.view(np.uint64), A.val.view(np.uint64)), (fmt, kw)
+
+
+def test_coo_canonicalisation_matches_oracle(torch):
+    for dt in (0, 1):
+        C = synth.rmat_coo(12, 60_000, seed=3, val_seed=4)
+        val = C.val.astype(np.float32) if dt == 1 else C.val
+        p, c, v = oracle.coo_to_csr(C.M, C.N, C.row, C.col, val.astype(np.float64))
+        if dt == 1:
+            v = v.astype(np.float32)  # duplicates are summed in FP64, rounded once
+        Ad = S.Matrix.from_coo(C.M, C.N, C.row, C.col, val, dt)
+        dp, dc, dv = Ad.to_csr()
+        assert np.array_equal(dp, p) and np.array_equal(dc, c)
+        assert np.array_equal(dv.view(np.uint32 if dt else np.uint64), v.view(np.uint32 if dt else np.uint64))
+    # duplicates summed left to right in input order
+    Ad = S.Matrix.from_coo(2, 2, [0, 1, 0, 0], [0, 1, 0, 0], np.array([1e16, 5.0, 1.0, -1e16]))
+    assert Ad.to_csr()[2].tolist() == [0.0, 5.0]
+
+
+# ------------------------------------------------------------ edges
+
+def test_nan_reaches_only_its_rows(torch):
+    A = synth.random_pattern(400, 300, 0.02, 5)
+    x64 = np.ones(300)
+    x64[7] = np.nan
+    touched = np.array([7 in A.col[A.ptr[i]:A.ptr[i + 1]] for i in range(400)])
+    Ad = S.Matrix.from_host(A)
+    x = device_vec(x64, 0)
+    for fmt, kw in FORMAT_CONFIGS:
+        y = Ad.convert(fmt, **kw).run(x).cpu().numpy()
+        assert np.array_equal(np.isnan(y), touched), (fmt, kw)
+
+
+def test_identity_permutation_and_zero_rows(torch):
+    n = 5000
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(n)
+    I = synth.HostCSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    Pm = synth.HostCSR(n, n, np.arange(n + 1, dtype=np.int32), perm.astype(np.int32), np.ones(n))
+    x64 = synth.vector(n, 3)
+    x = device_vec(x64, 0)
+    for A, want in [(I, x64), (Pm, x64[perm])]:
+        Ad = S.Matrix.from_host(A)
+        for fmt, kw in FORMAT_CONFIGS:
+            assert np.array_equal(Ad.convert(fmt, **kw).run(x).cpu().numpy(), want), (fmt, kw)
+
+
+def test_errors(torch):
+    A = S.Matrix.from_host(synth.laplace2d(8))
+    x = torch.ones(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(S.SpmvError) as e:
+        S.check(S.lib().spmv_run(S.FMT["ell"], A.h, S.dptr(x), S.dptr(x), S.stream()))
+    assert e.value.status == -1  # format mismatch
+    with pytest.raises(S.SpmvError) as e:
+        S.check(S.lib().spmv_run(S.FMT["csr"], A.h, S.dptr(x), S.dptr(x), S.stream()))
+    assert e.value.status == -1  # x == y
+    bad = [(np.array([0, 2, 1]), np.array([0, 1]), 2),        # ptr not monotone
+           (np.array([0, 2, 3]), np.array([1, 0, 1]), 2),     # unsorted
+           (np.array([0, 2, 3]), np.array([0, 0, 1]), 2),     # duplicate
+           (np.array([0, 2, 3]), np.array([0, 5, 1]), 2)]     # col >= N
+    for ptr, col, N in bad:
+        with pytest.raises(S.SpmvError) as e:
+            S.Matrix.from_csr(2, N, ptr, col, np.ones(len(col)))
+        assert e.value.status == -2
+    with pytest.raises(S.SpmvError) as e:
+        S.Matrix.from_coo(2, 2, [0, 2], [0, 0], np.ones(2))
+    assert e.value.status == -2
+    Z = S.Matrix.from_host(synth.zipf_rows(20_000, 20_000, 2.0, 16, 5_000, 4, 5))
+    with pytest.raises(S.SpmvError) as e:
+        Z.convert("ell", max_bytes=1 << 20)
+    assert e.value.status == -4
+
+
+def test_timing_protocol(torch):
+    A = S.Matrix.from_host(synth.laplace2d(64))
+    x = torch.ones(A.N, dtype=torch.float64, device="cuda")
+    y = torch.empty(A.M, dtype=torch.float64, device="cuda")
+    r = A.time(x, y, warmup=2, min_reps=20, max_reps=200, scrub_bytes=64 << 20)
+    assert r["reps"] >= 20 and 0 < r["min_ms"] <= r["median_ms"] < 10
