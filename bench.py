@@ -69,7 +69,7 @@ def cpu_baseline(work, budget_s=15.0):
             tot_t += time.perf_counter() - t0
             tot_bytes += A.nnz * 12 + 4 * (A.M + 1) + 8 * A.N + 8 * A.M
         reps += 1
-        if reps >= 200:
+        if reps >= 20000:
             break
     return {"value": round(tot_bytes / tot_t / 1e9, 3), "unit": "GB/s", "cores": int(used), "kind": "oracle",
             "sample": f"{reps} passes of y=Ax over both full matrices (FP64 CSR loop, OpenMP static rows)",
@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="", help="comma-separated matrix/format labels to run (default: all)")
+    ap.add_argument("--warm", action="store_true", help="skip the cache scrub between launches (labelled warm)")
+    ap.add_argument("--copy-probe", action="store_true", help="also time a plain 1 GiB device copy")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE), if present")
     args = ap.parse_args()
@@ -111,6 +114,8 @@ def main():
             except S.SpmvError as e:
                 log(f"[bench] {name}/{fmt}: not built ({e})")
                 continue
+            if args.only and f"{name}/{fmt}" not in args.only.split(","):
+                continue
             launches.append(dict(label=f"{name}/{fmt}", m=B, x=x, y=y, bytes=B.info.bytes_fmt,
                                  bytes_min=B.info.bytes_min, nnz=A.nnz, params=B.params))
         del base
@@ -121,7 +126,8 @@ def main():
 
     def step(record):
         for L in launches:
-            S.scrub(SCRUB)
+            if not args.warm:
+                S.scrub(SCRUB)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -170,9 +176,11 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded generators)",
            "config": {"workload": "27-pt stencil 100^3 (26.46M nnz) + Zipf(2) 1Mx1M (16M nnz), FP64, int32 "
-                                  "indices, all formats, cold cache",
+                                  "indices, all formats, " + ("warm cache" if args.warm else "cold cache"),
                       "launches_per_step": len(launches)},
            "roofline": roof, "per_format": per}
+    if args.copy_probe:
+        out["copy_probe_GBps"] = round(S.copy_probe(1 << 30, 20), 1)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(work)

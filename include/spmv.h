@@ -71,7 +71,8 @@ typedef struct {
   uint32_t flags;            /* SPMV_FLAG_* */
 } spmv_params_t;
 
-#define SPMV_FLAG_NO_CHECK 1u /* skip the structural validation of spmv_mat_from_csr */
+#define SPMV_FLAG_NO_CHECK 1u /* skip the column checks of spmv_mat_from_csr (ptr is always checked) */
+#define SPMV_FLAG_CSR_WAVES 2u /* CSR: per-wave row units (+ long-row segments) instead of workgroup row blocks */
 
 typedef struct {
   int32_t fmt, dtype;

@@ -49,6 +49,9 @@ int64_t bytes_min(const spmv_mat_s* A) {
 }
 
 spmv_status_t dispatch_run(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  // the kernels address x, and ELL/SELL columns, with 32-bit byte offsets
+  if (A->N * A->sv >= ((int64_t)1 << 32) || A->M * A->sv >= ((int64_t)1 << 32))
+    return fail(SPMV_ERR_UNSUPPORTED, "x or y larger than 4 GiB");
   switch (A->fmt) {
     case SPMV_FMT_CSR: return run_csr(A, x, y, s);
     case SPMV_FMT_CSR5: return run_csr5(A, x, y, s);

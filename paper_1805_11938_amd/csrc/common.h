@@ -60,6 +60,9 @@ inline hipStream_t hs(spmv_stream_t s) { return reinterpret_cast<hipStream_t>(s)
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int value_size(spmv_dtype_t dt) { return dt == SPMV_F64 ? 8 : 4; }
 int64_t default_max_bytes();
+// Workgroups that fit on the device at once when each CU holds per_cu of them
+// (persistent kernels size their grid with it).
+int64_t resident_blocks(int per_cu);
 
 }  // namespace spmv
 
@@ -77,6 +80,12 @@ struct spmv_mat_s {
   void* val = nullptr;
   int32_t* blk_row = nullptr;  // CSR row blocks: block b owns rows [blk_row[b], blk_row[b+1])
   int64_t nblk = 0;
+  int32_t* unit_row = nullptr; // CSR wave units: unit u owns rows [unit_row[u], unit_row[u+1])
+  int64_t nunits = 0;
+  int64_t nseg = 0, nlong = 0; // CSR long rows cut into segments
+  int2* segs = nullptr;        // (row, first nonzero) per segment
+  int4* longs = nullptr;       // (row, first segment, segment count) per long row
+  double* seg_part = nullptr;  // segment partial sums (run scratch)
 
   // ELL, and the ELL part of HYB: column-major M x K, slot (i,k) at k*M + i
   int64_t K = 0;
@@ -90,6 +99,10 @@ struct spmv_mat_s {
   int64_t* cs = nullptr;    // nchunks + 1 slot offsets
   int32_t* scol = nullptr;
   void* sval = nullptr;
+  int64_t nitems = 0, nwide = 0;  // column-slice work items; chunks split into several slices
+  int2* items = nullptr;          // (chunk, first column) per item
+  int4* wide = nullptr;           // (chunk, first item, item count) per split chunk
+  double* part = nullptr;         // nitems * C partial sums (run scratch, split chunks only)
 
   // HYB COO part (row-major) and its row-aligned block boundaries
   int64_t ncoo = 0, ncoo_blk = 0;
@@ -178,6 +191,22 @@ __device__ __forceinline__ T ldnt(const T* p) {
   return __builtin_nontemporal_load(p);
 }
 
+// Loads at a wave-uniform base plus a 32-bit per-lane element offset: the
+// compiler can then use the scalar-base addressing form (one VGPR per
+// address instead of a 64-bit pair), which keeps more loads in flight.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+  return *(const T*)((const char*)base + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T ldnt32(const T* base, uint32_t idx) {
+  return __builtin_nontemporal_load((const T*)((const char*)base + idx * (uint32_t)sizeof(T)));
+}
+
+// Keeps the compiler from moving work across this point: used after a batch
+// of independent loads so that all of them are issued before the first wait.
+__device__ __forceinline__ void issue_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
 // Sum over aligned groups of G lanes (G a power of two <= 64).
@@ -218,20 +247,25 @@ __device__ __forceinline__ double block_sum(double v, double* sh /* >= 4 doubles
 }
 
 // sum of val[k] * x[col[k]] over k = a + first, a + first + stride, ... < e
-// (two independent accumulators, non-temporal loads of the matrix streams)
+// (four independent loads per step, non-temporal loads of the matrix streams)
 template <typename T>
 __device__ __forceinline__ double row_dot(const int32_t* __restrict__ col, const T* __restrict__ val,
                                           const T* __restrict__ x, int64_t a, int64_t e, int first, int stride) {
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t k = a + first;
-  for (; k + stride < e; k += 2 * stride) {
-    const int32_t c0 = ldnt(col + k), c1 = ldnt(col + k + stride);
-    const T v0 = ldnt(val + k), v1 = ldnt(val + k + stride);
-    s0 += (double)v0 * (double)x[c0];
-    s1 += (double)v1 * (double)x[c1];
+  for (; k + 3 * stride < e; k += 4 * stride) {
+    const int32_t c0 = ldnt(col + k), c1 = ldnt(col + k + stride), c2 = ldnt(col + k + 2 * stride),
+                  c3 = ldnt(col + k + 3 * stride);
+    const T v0 = ldnt(val + k), v1 = ldnt(val + k + stride), v2 = ldnt(val + k + 2 * stride),
+            v3 = ldnt(val + k + 3 * stride);
+    const T x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+    s0 += (double)v0 * (double)x0;
+    s1 += (double)v1 * (double)x1;
+    s2 += (double)v2 * (double)x2;
+    s3 += (double)v3 * (double)x3;
   }
-  if (k < e) s0 += (double)ldnt(val + k) * (double)x[ldnt(col + k)];
-  return s0 + s1;
+  for (; k < e; k += stride) s0 += (double)ldnt(val + k) * (double)x[ldnt(col + k)];
+  return (s0 + s1) + (s2 + s3);
 }
 
 }  // namespace spmv

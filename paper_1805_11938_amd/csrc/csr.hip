@@ -23,6 +23,9 @@ constexpr int CSR_W = 2048;    // rows + nonzeros per row block
 constexpr int CSR_CAP = 2560;  // nonzeros a block can stage in LDS
 constexpr int CSR_IT = CSR_CAP / BS;
 constexpr int CSR_LONG = 4096; // rows at least this long are reduced by a whole block
+constexpr int WU_ROWS = 512;   // rows + nonzeros per wave unit (see k_csr_waves)
+constexpr int LONG_ROW = 1024; // rows longer than this are cut into segments for several waves
+constexpr int SEG = 512;       // nonzeros per long-row segment
 
 static_assert(CSR_CAP % BS == 0, "CAP must be a multiple of the block size");
 
@@ -70,13 +73,13 @@ static spmv_status_t validate_csr(spmv_mat_s* A, int check_cols, hipStream_t s) 
 }
 
 // ------------------------------------------------------------ row blocks
-__global__ void k_csr_blocks(const int32_t* ptr, int64_t M, int64_t nblk, int32_t* blk_row) {
+__global__ void k_csr_blocks(const int32_t* ptr, int64_t M, int64_t nblk, int64_t width, int32_t* blk_row) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nblk; b += (int64_t)gridDim.x * blockDim.x) {
     if (b == nblk) {
       blk_row[b] = (int32_t)M;
       continue;
     }
-    const int64_t target = b * CSR_W;
+    const int64_t target = b * width;
     int64_t lo = 0, hi = M;  // first r in [0, M) with r + ptr[r] >= target, else M
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
@@ -87,65 +90,128 @@ __global__ void k_csr_blocks(const int32_t* ptr, int64_t M, int64_t nblk, int32_
   }
 }
 
-spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s) {
-  A->nblk = cdiv(A->M + A->nnz, CSR_W);
-  if (A->nblk < 1) A->nblk = 1;
-  SPMV_TRY(mat_alloc(A, (void**)&A->blk_row, sizeof(int32_t) * (A->nblk + 1)));
-  int64_t g = cdiv(A->nblk + 1, BS);
+static spmv_status_t build_partition(spmv_mat_s* A, int64_t width, int64_t* n, int32_t** rows, hipStream_t s) {
+  *n = cdiv(A->M + A->nnz, width);
+  if (*n < 1) *n = 1;
+  SPMV_TRY(mat_alloc(A, (void**)rows, sizeof(int32_t) * (*n + 1)));
+  int64_t g = cdiv(*n + 1, BS);
   if (g > 65536) g = 65536;
-  k_csr_blocks<<<(unsigned)g, BS, 0, s>>>(A->ptr, A->M, A->nblk, A->blk_row);
+  k_csr_blocks<<<(unsigned)g, BS, 0, s>>>(A->ptr, A->M, *n, width, *rows);
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
 }
 
-// ------------------------------------------------------------ kernels
-__device__ __forceinline__ int lanes_for(int64_t nz, int64_t rows) {
-  const int64_t avg = rows > 0 ? nz / rows : 0;
-  if (avg >= 128) return 64;
-  if (avg >= 64) return 32;
-  if (avg >= 32) return 16;
-  if (avg >= 16) return 8;
-  if (avg >= 8) return 4;
-  if (avg >= 4) return 2;
-  return 1;
+// Row partitions of a CSR handle: workgroup-sized blocks (batched launch)
+// and wave-sized units (the default kernel).
+__global__ void k_long_count(int64_t M, const int32_t* ptr, int32_t* nseg, int32_t* islong) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t len = ptr[r + 1] - ptr[r];
+    nseg[r] = len > LONG_ROW ? (int32_t)((len + SEG - 1) / SEG) : 0;
+    islong[r] = len > LONG_ROW;
+  }
 }
+
+__global__ void k_long_fill(int64_t M, const int32_t* ptr, const int32_t* nseg, const int32_t* sbase,
+                            const int32_t* lpos, int2* segs, int4* longs) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t n = nseg[r];
+    if (!n) continue;
+    for (int32_t j = 0; j < n; ++j) segs[sbase[r] + j] = make_int2((int)r, ptr[r] + j * SEG);
+    longs[lpos[r]] = make_int4((int)r, sbase[r], n, 0);
+  }
+}
+
+spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s) {
+  SPMV_TRY(build_partition(A, CSR_W, &A->nblk, &A->blk_row, s));
+  SPMV_TRY(build_partition(A, WU_ROWS, &A->nunits, &A->unit_row, s));
+  const int64_t M = A->M;
+  A->nseg = A->nlong = 0;
+  if (M == 0) return SPMV_OK;
+  DTmp ns, il, sb, lp;
+  SPMV_TRY(ns.alloc(sizeof(int32_t) * M));
+  SPMV_TRY(il.alloc(sizeof(int32_t) * M));
+  SPMV_TRY(sb.alloc(sizeof(int32_t) * (M + 1)));
+  SPMV_TRY(lp.alloc(sizeof(int32_t) * (M + 1)));
+  const unsigned g = (unsigned)std::min<int64_t>(cdiv(M, BS), 65536);
+  k_long_count<<<g, BS, 0, s>>>(M, A->ptr, ns.as<int32_t>(), il.as<int32_t>());
+  SPMV_LAUNCH_CHECK();
+  SPMV_TRY(scan_i32_to_i32(ns.as<int32_t>(), sb.as<int32_t>(), M, s));
+  SPMV_TRY(scan_i32_to_i32(il.as<int32_t>(), lp.as<int32_t>(), M, s));
+  int32_t h[2] = {0, 0};
+  SPMV_TRY(copy_to_host(&h[0], sb.as<int32_t>() + M, sizeof(int32_t), s));
+  SPMV_TRY(copy_to_host(&h[1], lp.as<int32_t>() + M, sizeof(int32_t), s));
+  A->nseg = h[0];
+  A->nlong = h[1];
+  if (A->nlong == 0) return SPMV_OK;
+  SPMV_TRY(mat_alloc(A, (void**)&A->segs, sizeof(int2) * A->nseg));
+  SPMV_TRY(mat_alloc(A, (void**)&A->longs, sizeof(int4) * A->nlong));
+  SPMV_TRY(mat_alloc(A, (void**)&A->seg_part, sizeof(double) * A->nseg));
+  k_long_fill<<<g, BS, 0, s>>>(M, A->ptr, ns.as<int32_t>(), sb.as<int32_t>(), lp.as<int32_t>(), A->segs, A->longs);
+  SPMV_LAUNCH_CHECK();
+  SPMV_HIP(hipStreamSynchronize(s));
+  return SPMV_OK;
+}
+
+// ------------------------------------------------------------ kernels
+// Lanes per row for the LDS reduction: enough lanes that the block's rows
+// are covered in one pass, but no more than the mean row length needs.
+__device__ __forceinline__ int lanes_for(int64_t nz, int64_t rows) {
+  int V = 1;
+  while (V < 64 && V * 2 * rows <= BS) V *= 2;
+  const int64_t avg = rows > 0 ? nz / rows : 0;
+  while (V > 1 && V > avg) V >>= 1;
+  return V;
+}
+
+constexpr int CSR_RCAP = 512;  // row pointers a block stages in LDS
 
 // One row block (all threads of the workgroup call this with the same rows).
 template <typename T>
 __device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, const int32_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col, const T* __restrict__ val,
-                                               const T* __restrict__ x, T* __restrict__ y, double* prod) {
+                                               const T* __restrict__ x, T* __restrict__ y, double* prod,
+                                               int32_t* sptr) {
   if (r0 >= r1) return;
   const int t = threadIdx.x;
   const int64_t k0 = ptr[r0], k1 = ptr[r1];
-  const int64_t E = k1 - k0;
+  const int64_t E = k1 - k0, nr = r1 - r0;
   if (E <= CSR_CAP) {
-    int32_t c[CSR_IT];
-    T v[CSR_IT];
+    const bool staged = nr <= CSR_RCAP;
+    if (staged)
+      for (int64_t i = t; i <= nr; i += BS) sptr[i] = ptr[r0 + i] - (int32_t)k0;
+    if (E > 0) {  // clamped, branch-free loads and gathers keep every request in flight
+      int32_t c[CSR_IT];
+      T v[CSR_IT], xv[CSR_IT];
+      const int32_t* cb = col + k0;  // block-uniform bases, 32-bit lane offsets
+      const T* vb = val + k0;
 #pragma unroll
-    for (int j = 0; j < CSR_IT; ++j) {
-      const int64_t k = t + j * BS;
-      if (k < E) {
-        c[j] = ldnt(col + k0 + k);
-        v[j] = ldnt(val + k0 + k);
+      for (int j = 0; j < CSR_IT; ++j) {
+        const uint32_t k = (uint32_t)(t + j * BS), kk = k < (uint32_t)E ? k : (uint32_t)E - 1;
+        c[j] = ldnt32(cb, kk);
+        v[j] = ldnt32(vb, kk);
+      }
+      issue_fence();
+#pragma unroll
+      for (int j = 0; j < CSR_IT; ++j) xv[j] = ld32(x, (uint32_t)c[j]);
+      issue_fence();
+#pragma unroll
+      for (int j = 0; j < CSR_IT; ++j) {
+        const int64_t k = t + j * BS;
+        if (k < E) prod[k] = (double)v[j] * (double)xv[j];
       }
     }
-#pragma unroll
-    for (int j = 0; j < CSR_IT; ++j) {
-      const int64_t k = t + j * BS;
-      if (k < E) prod[k] = (double)v[j] * (double)x[c[j]];
-    }
     __syncthreads();
-    const int V = lanes_for(E, r1 - r0);
+    const int V = lanes_for(E, nr);
     const int g = t / V, lane = t % V, ng = BS / V;
-    for (int64_t r = r0 + g; r < r1; r += ng) {
-      const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
+    for (int64_t r = g; r < nr; r += ng) {
+      const int a = staged ? sptr[r] : ptr[r0 + r] - (int32_t)k0;
+      const int e = staged ? sptr[r + 1] : ptr[r0 + r + 1] - (int32_t)k0;
       double s = 0.0;
       for (int k = a + lane; k < e; k += V) s += prod[k];
       s = group_sum_rt(s, V);
-      if (lane == 0) y[r] = (T)s;
+      if (lane == 0) y[r0 + r] = (T)s;
     }
-    __syncthreads();  // prod may be reused by the caller's next block
+    __syncthreads();  // prod / sptr may be reused by the caller's next block
     return;
   }
   // long path: a wave per row below CSR_LONG, the whole block above
@@ -170,9 +236,136 @@ __global__ __launch_bounds__(BS) void k_csr_rows(int64_t nblk, const int32_t* __
                                                  const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                  const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
   __shared__ double prod[CSR_CAP];
+  __shared__ int32_t sptr[CSR_RCAP + 1];
   const uint32_t b = XCD ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   if (b >= nblk) return;
-  csr_rows_block<T>(blk_row[b], blk_row[b + 1], ptr, col, val, x, y, prod);
+  csr_rows_block<T>(blk_row[b], blk_row[b + 1], ptr, col, val, x, y, prod, sptr);
+}
+
+// ------------------------------------------------------------ wave units
+// Default CSR kernel: the same merged (rows + nonzeros) split, in units of
+// WU for one wave each.  Waves never wait on each other (no workgroup
+// barrier), so the load, gather and reduce phases of the 4 x 8 resident
+// waves per SIMD overlap freely.  Each wave stages its unit's row pointers
+// and products in its own LDS slice; rows longer than the slice are summed
+// straight from global memory by the whole wave.
+constexpr int WU = WU_ROWS;         // rows + nonzeros per wave unit
+constexpr int WCAP = 512;           // products a wave stages in LDS
+constexpr int WIT = WCAP / WAVE;
+constexpr int WRCAP = 128;          // row pointers a wave stages in LDS
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_lanes_for(int64_t nz, int64_t rows) {
+  int V = 1;
+  while (V < 64 && V * 2 * rows <= WAVE) V *= 2;
+  const int64_t avg = rows > 0 ? nz / rows : 0;
+  while (V > 1 && V > avg) V >>= 1;
+  return V;
+}
+
+template <typename T>
+__device__ __forceinline__ void csr_rows_wave(int64_t r0, int64_t r1, const int32_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const T* __restrict__ x, T* __restrict__ y, double* prod,
+                                              int32_t* sptr) {
+  if (r0 >= r1) return;
+  const int lane = __lane_id();
+  const int64_t k0 = __builtin_amdgcn_readfirstlane(ptr[r0]), k1 = __builtin_amdgcn_readfirstlane(ptr[r1]);
+  const int64_t E = k1 - k0, nr = r1 - r0;
+  if (E <= WCAP && nr <= WRCAP) {
+    for (int64_t i = lane; i <= nr; i += WAVE) sptr[i] = ptr[r0 + i] - (int32_t)k0;
+    if (E > 0) {
+      int32_t c[WIT];
+      T v[WIT], xv[WIT];
+      const int32_t* cb = col + k0;  // wave-uniform bases, 32-bit lane offsets
+      const T* vb = val + k0;
+      const uint32_t Em1 = (uint32_t)E - 1;
+#pragma unroll
+      for (int j = 0; j < WIT; ++j) {
+        const uint32_t k = (uint32_t)(lane + j * WAVE), kk = k < (uint32_t)E ? k : Em1;
+        c[j] = ldnt32(cb, kk);
+        v[j] = ldnt32(vb, kk);
+      }
+      issue_fence();
+#pragma unroll
+      for (int j = 0; j < WIT; ++j) xv[j] = ld32(x, (uint32_t)c[j]);
+      issue_fence();
+#pragma unroll
+      for (int j = 0; j < WIT; ++j) {
+        const int64_t k = lane + j * WAVE;
+        if (k < E) prod[k] = (double)v[j] * (double)xv[j];
+      }
+    }
+    wave_lds_sync();
+    const int V = wave_lanes_for(E, nr);
+    const int g = lane / V, gl = lane % V, ng = WAVE / V;
+    for (int64_t r = g; r < nr; r += ng) {
+      const int a = sptr[r], e = sptr[r + 1];
+      double s0 = 0.0, s1 = 0.0;
+      int k = a + gl;
+      for (; k + V < e; k += 2 * V) {
+        s0 += prod[k];
+        s1 += prod[k + V];
+      }
+      if (k < e) s0 += prod[k];
+      const double sum = group_sum_rt(s0 + s1, V);
+      if (gl == 0) y[r0 + r] = (T)sum;
+    }
+    wave_lds_sync();  // the slice is reused by the wave's next unit
+    return;
+  }
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t a = ptr[r], e = ptr[r + 1];
+    if (e - a > LONG_ROW) continue;  // summed by the segment waves
+    const double sum = group_sum<64>(row_dot(col, val, x, a, e, lane, WAVE));
+    if (lane == 0) y[r] = (T)sum;
+  }
+}
+
+// Waves u < nunits take wave units; waves nunits + j take segment j of a
+// long row (SEG nonzeros, partial sum to part[j]).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_waves(int64_t nunits, const int32_t* __restrict__ unit_row, int64_t nseg,
+                                                  const int2* __restrict__ segs, double* __restrict__ part,
+                                                  const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                  const T* __restrict__ val, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
+  __shared__ double prod[BS / WAVE][WCAP];
+  __shared__ int32_t sptr[BS / WAVE][WRCAP + 1];
+  // the wave index is uniform: keep it (and everything derived) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int64_t nw = (int64_t)gridDim.x * (BS / WAVE);
+  for (int64_t u = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (BS / WAVE) + w; u < nunits + nseg; u += nw) {
+    if (u < nunits) {
+      const int32_t r0 = __builtin_amdgcn_readfirstlane(unit_row[u]);
+      const int32_t r1 = __builtin_amdgcn_readfirstlane(unit_row[u + 1]);
+      csr_rows_wave<T>(r0, r1, ptr, col, val, x, y, prod[w], sptr[w]);
+    } else {
+      const int2 sg = segs[u - nunits];  // (row, first nonzero)
+      const int64_t e = ptr[sg.x + 1];
+      const int64_t kb = sg.y, ke = kb + SEG < e ? kb + SEG : e;
+      const double sum = group_sum<64>(row_dot(col, val, x, kb, ke, __lane_id(), WAVE));
+      if (__lane_id() == 0) part[u - nunits] = sum;
+    }
+  }
+}
+
+// one wave per long row: its segment partials summed in order
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_long_fix(int64_t nlong, const int4* __restrict__ longs,
+                                                     const double* __restrict__ part, T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * (BS / WAVE) + threadIdx.x / WAVE;
+  if (i >= nlong) return;
+  const int4 L = longs[i];  // row, first segment, segment count
+  double s = 0.0;
+  for (int j = __lane_id(); j < L.z; j += WAVE) s += part[L.y + j];
+  s = group_sum<64>(s);
+  if (__lane_id() == 0) y[L.x] = (T)s;
 }
 
 template <typename T, int V>
@@ -193,7 +386,18 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   const int32_t* ptr = A->ptr;
   const T* val = (const T*)A->val;
   if (V == 0) {
-    k_csr_rows<T, true><<<(unsigned)A->nblk, BS, 0, s>>>(A->nblk, A->blk_row, ptr, A->col, val, x, y);
+    if (!(A->params.flags & SPMV_FLAG_CSR_WAVES))
+      k_csr_rows<T, true><<<(unsigned)A->nblk, BS, 0, s>>>(A->nblk, A->blk_row, ptr, A->col, val, x, y);
+    else
+    {
+      const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nunits + A->nseg, BS / WAVE), resident_blocks(8));
+      k_csr_waves<T><<<g, BS, 0, s>>>(
+          A->nunits, A->unit_row, A->nseg, A->segs, A->seg_part, ptr, A->col, val, x, y);
+      if (A->nlong > 0) {
+        SPMV_LAUNCH_CHECK();
+        k_csr_long_fix<T><<<(unsigned)cdiv(A->nlong, BS / WAVE), BS, 0, s>>>(A->nlong, A->longs, A->seg_part, y);
+      }
+    }
   } else {
     const unsigned g = (unsigned)cdiv(A->M, BS / V);
     switch (V) {
@@ -232,6 +436,7 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_csr_batched(int32_t n, int64_t nitems, const BatchDesc* __restrict__ desc,
                                                     const void* const* __restrict__ xs, void* const* __restrict__ ys) {
   __shared__ double prod[CSR_CAP];
+  __shared__ int32_t sptr[CSR_RCAP + 1];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     int lo = 0, hi = n - 1;  // last matrix with item0 <= it
     while (lo < hi) {
@@ -242,7 +447,7 @@ __global__ __launch_bounds__(BS) void k_csr_batched(int32_t n, int64_t nitems, c
     const BatchDesc d = desc[lo];
     const int64_t b = it - d.item0;
     csr_rows_block<T>(d.blk_row[b], d.blk_row[b + 1], d.ptr, d.col, (const T*)d.val, (const T*)xs[lo], (T*)ys[lo],
-                      prod);
+                      prod, sptr);
   }
 }
 

@@ -339,22 +339,15 @@ __device__ void c5_tail(const C5Args& a, const T* __restrict__ val, const T* __r
   }
 }
 
-template <typename T, int SIG, bool EMPTY>
-__global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val, const T* __restrict__ x,
-                                             T* __restrict__ y) {
-  if ((int64_t)blockIdx.x == a.nb_main) {
-    c5_tail<T>(a, val, x, y);
-    return;
-  }
-  const int omega = a.omega;
+// One tile (omega lanes).  t and row0 are wave-uniform when W64.
+template <typename T, int SIG, bool EMPTY, bool W64>
+__device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const T* __restrict__ val,
+                                        const T* __restrict__ x, T* __restrict__ y) {
+  const int omega = W64 ? WAVE : a.omega;
   const int sigma = SIG > 0 ? SIG : a.sigma;
-  const int tpb = BS / omega;
-  const int l = threadIdx.x % omega;
-  const int64_t t = (int64_t)blockIdx.x * tpb + threadIdx.x / omega;
-  if (t >= a.ntiles) return;  // whole tiles (aligned lane groups) leave together
   const int64_t W = (int64_t)omega * sigma, base = t * W;
   const uint32_t F = a.flags[t * omega + l];
-  const int64_t row0 = a.tile_ptr[t];
+  const int64_t row0 = W64 ? (int64_t)__builtin_amdgcn_readfirstlane(a.tile_ptr[t]) : (int64_t)a.tile_ptr[t];
   const bool cont = a.ptr[row0] < base;
   const int64_t nzb = EMPTY ? a.nzbase[t] : 0;
   // y_off: flags in earlier lanes of the tile
@@ -370,12 +363,18 @@ __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val
   int lf = 0;
   if (SIG > 0) {
     int32_t c[SIG > 0 ? SIG : 1];
-    T v[SIG > 0 ? SIG : 1];
+    T v[SIG > 0 ? SIG : 1], xv[SIG > 0 ? SIG : 1];
+    const int32_t* cb = a.col + base;  // tile base (wave-uniform when W64)
+    const T* vb = val + base;
 #pragma unroll
     for (int i = 0; i < SIG; ++i) {
-      c[i] = ldnt(a.col + base + (int64_t)i * omega + l);
-      v[i] = ldnt(val + base + (int64_t)i * omega + l);
+      c[i] = ldnt32(cb, (uint32_t)(i * omega + l));
+      v[i] = ldnt32(vb, (uint32_t)(i * omega + l));
     }
+    issue_fence();
+#pragma unroll
+    for (int i = 0; i < SIG; ++i) xv[i] = ld32(x, (uint32_t)c[i]);
+    issue_fence();
 #pragma unroll
     for (int i = 0; i < SIG; ++i) {
       if ((F >> i) & 1u) {
@@ -385,7 +384,7 @@ __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val
         acc = 0.0;
         ++lf;
       }
-      acc += (double)v[i] * (double)x[c[i]];
+      acc += (double)v[i] * (double)xv[i];
     }
   } else {
     for (int i = 0; i < sigma; ++i) {
@@ -419,6 +418,21 @@ __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val
   if (seen) c5_write<T, EMPTY>(a, t, row0, nzb, cont, yoff + lf - 1, acc + S, y);
 }
 
+// Persistent: each lane group loops over tiles; the last workgroup then
+// sums the CSR-ordered tail.
+template <typename T, int SIG, bool EMPTY, bool W64>
+__global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val, const T* __restrict__ x,
+                                             T* __restrict__ y) {
+  const int omega = W64 ? WAVE : a.omega;
+  const int tpb = BS / omega;
+  const int l = threadIdx.x % omega;
+  const int64_t step = (int64_t)gridDim.x * tpb;
+  const int64_t first = W64 ? (int64_t)blockIdx.x * tpb + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE)
+                            : (int64_t)blockIdx.x * tpb + threadIdx.x / omega;
+  for (int64_t t = first; t < a.ntiles; t += step) c5_tile<T, SIG, EMPTY, W64>(a, t, l, val, x, y);
+  if (blockIdx.x == gridDim.x - 1) c5_tail<T>(a, val, x, y);
+}
+
 template <typename T>
 __global__ __launch_bounds__(BS) void k_csr5_fix(int64_t nchains, const int32_t* __restrict__ chains,
                                                  const double* __restrict__ carry, T* __restrict__ y) {
@@ -431,15 +445,21 @@ __global__ __launch_bounds__(BS) void k_csr5_fix(int64_t nchains, const int32_t*
   if (__lane_id() == 0) y[row] = (T)((double)y[row] + s);
 }
 
+template <typename T, bool EMPTY, bool W64>
+static void launch_c5w(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
+  switch (a.sigma) {
+    case 4: k_csr5<T, 4, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
+    case 8: k_csr5<T, 8, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
+    case 16: k_csr5<T, 16, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
+    case 32: k_csr5<T, 32, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
+    default: k_csr5<T, 0, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
+  }
+}
+
 template <typename T, bool EMPTY>
 static void launch_c5(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
-  switch (a.sigma) {
-    case 4: k_csr5<T, 4, EMPTY><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    case 8: k_csr5<T, 8, EMPTY><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    case 16: k_csr5<T, 16, EMPTY><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    case 32: k_csr5<T, 32, EMPTY><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    default: k_csr5<T, 0, EMPTY><<<grid, BS, 0, s>>>(a, val, x, y); break;
-  }
+  if (a.omega == WAVE) launch_c5w<T, EMPTY, true>(a, grid, val, x, y, s);
+  else launch_c5w<T, EMPTY, false>(a, grid, val, x, y, s);
 }
 
 template <typename T>
@@ -463,7 +483,7 @@ static spmv_status_t run_csr5_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) 
   a.tail_rlo = A->tail_rlo;
   a.tail_row = A->c5_tail_row;
   a.carry = A->carry;
-  const unsigned grid = (unsigned)(a.nb_main + 1);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(a.nb_main, resident_blocks(8)));
   if (A->has_empty) launch_c5<T, true>(a, grid, (const T*)A->val, x, y, s);
   else launch_c5<T, false>(a, grid, (const T*)A->val, x, y, s);
   SPMV_LAUNCH_CHECK();

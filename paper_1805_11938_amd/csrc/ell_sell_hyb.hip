@@ -72,36 +72,110 @@ __global__ void k_ell_to_csr(int64_t M, const int32_t* ecol, const T* eval, cons
   }
 }
 
+// Eight slots per step: all 16 loads of a step are issued before the x
+// gathers, so each wave keeps many requests in flight.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_ell(int64_t M, int64_t K, const int32_t* __restrict__ ecol,
                                             const T* __restrict__ eval, const T* __restrict__ x, T* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= M) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < M; i += (int64_t)gridDim.x * BS) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
   int64_t k = 0;
-  for (; k + 3 < K; k += 4) {
-    const int64_t q = k * M + i;
-    const int32_t c0 = ldnt(ecol + q), c1 = ldnt(ecol + q + M), c2 = ldnt(ecol + q + 2 * M), c3 = ldnt(ecol + q + 3 * M);
-    const T v0 = ldnt(eval + q), v1 = ldnt(eval + q + M), v2 = ldnt(eval + q + 2 * M), v3 = ldnt(eval + q + 3 * M);
-    if (c0 >= 0) s0 += (double)v0 * (double)x[c0];
-    if (c1 >= 0) s1 += (double)v1 * (double)x[c1];
-    if (c2 >= 0) s2 += (double)v2 * (double)x[c2];
-    if (c3 >= 0) s3 += (double)v3 * (double)x[c3];
+  for (; k + 7 < K; k += 8) {
+    int32_t c[8];
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = ldnt32(ecol + (k + u) * M, (uint32_t)i);  // uniform column base
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ldnt32(eval + (k + u) * M, (uint32_t)i);
+    issue_fence();
+    T xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = ld32(x, (uint32_t)(c[u] >= 0 ? c[u] : 0));  // branch-free gathers
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u & 3] += c[u] >= 0 ? (double)v[u] * (double)xv[u] : 0.0;
   }
   for (; k < K; ++k) {
-    const int64_t q = k * M + i;
-    const int32_t c = ldnt(ecol + q);
-    const T v = ldnt(eval + q);
-    if (c >= 0) s0 += (double)v * (double)x[c];
+    const int32_t c = ldnt(ecol + k * M + i);
+    const T v = ldnt(eval + k * M + i);
+    const T xv = x[c >= 0 ? c : 0];
+    s[0] += c >= 0 ? (double)v * (double)xv : 0.0;
   }
-  y[i] = (T)((s0 + s1) + (s2 + s3));
+  y[i] = (T)((s[0] + s[1]) + (s[2] + s[3]));
+  }
+}
+
+// Two adjacent rows per lane (M even): the column and value slots of a row
+// pair are loaded as one 8-byte and one 16-byte vector, halving the number of
+// load instructions per byte.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct Vec2<float> {
+  typedef float __attribute__((ext_vector_type(2))) type;
+};
+typedef int32_t __attribute__((ext_vector_type(2))) i32x2;
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_ell2(int64_t M, int64_t K, const int32_t* __restrict__ ecol,
+                                             const T* __restrict__ eval, const T* __restrict__ x,
+                                             T* __restrict__ y) {
+  typedef typename Vec2<T>::type T2;
+  const int64_t M2 = M >> 1;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < M2; i += (int64_t)gridDim.x * BS) {
+    double s0[2] = {0.0, 0.0}, s1[2] = {0.0, 0.0};
+    int64_t k = 0;
+    for (; k + 3 < K; k += 4) {
+      i32x2 c[4];
+      T2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = ldnt32((const i32x2*)(ecol + (k + u) * M), (uint32_t)i);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = ldnt32((const T2*)(eval + (k + u) * M), (uint32_t)i);
+      issue_fence();
+      T xa[4], xb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        xa[u] = ld32(x, (uint32_t)(c[u].x >= 0 ? c[u].x : 0));
+        xb[u] = ld32(x, (uint32_t)(c[u].y >= 0 ? c[u].y : 0));
+      }
+      issue_fence();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s0[u & 1] += c[u].x >= 0 ? (double)v[u].x * (double)xa[u] : 0.0;
+        s1[u & 1] += c[u].y >= 0 ? (double)v[u].y * (double)xb[u] : 0.0;
+      }
+    }
+    for (; k < K; ++k) {
+      const i32x2 c = ldnt32((const i32x2*)(ecol + k * M), (uint32_t)i);
+      const T2 v = ldnt32((const T2*)(eval + k * M), (uint32_t)i);
+      const T xa = ld32(x, (uint32_t)(c.x >= 0 ? c.x : 0)), xb = ld32(x, (uint32_t)(c.y >= 0 ? c.y : 0));
+      s0[0] += c.x >= 0 ? (double)v.x * (double)xa : 0.0;
+      s1[0] += c.y >= 0 ? (double)v.y * (double)xb : 0.0;
+    }
+    T2 out;
+    out.x = (T)(s0[0] + s0[1]);
+    out.y = (T)(s1[0] + s1[1]);
+    *(T2*)(y + 2 * i) = out;
+  }
 }
 
 template <typename T>
 static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const void* eval, const void* x, void* y,
                                 hipStream_t s) {
   if (M == 0) return SPMV_OK;
-  k_ell<T><<<(unsigned)cdiv(M, BS), BS, 0, s>>>(M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
+  if ((M & 1) == 0 && ((uintptr_t)y & (2 * sizeof(T) - 1)) == 0) {
+    const unsigned g2 = (unsigned)std::min<int64_t>(cdiv(M / 2, BS), resident_blocks(8));
+    k_ell2<T><<<g2, BS, 0, s>>>(M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
+    SPMV_LAUNCH_CHECK();
+    return SPMV_OK;
+  }
+  const unsigned g = (unsigned)std::min<int64_t>(cdiv(M, BS), resident_blocks(8));  // persistent grid
+  k_ell<T><<<g, BS, 0, s>>>(M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
 }
@@ -228,45 +302,94 @@ __global__ void k_sell_to_csr(int64_t M, int64_t Mpad, int C, const int32_t* per
   }
 }
 
+// A work item is a slice of at most SELL_KT columns of one chunk, run by C
+// lanes (one per stored row).  Chunks of one slice write y directly; wider
+// chunks write per-slice partial sums that k_sell_fix adds in slice order.
+constexpr int SELL_KT = 64;
+
 template <typename T, int LOGC, bool PERM>
-__global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t Mpad, const int64_t* __restrict__ cs,
-                                             const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
-                                             const T* __restrict__ sval, const T* __restrict__ x, T* __restrict__ y) {
+__global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const int2* __restrict__ items,
+                                             const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
+                                             const int32_t* __restrict__ scol, const T* __restrict__ sval,
+                                             const T* __restrict__ x, T* __restrict__ y, double* __restrict__ part) {
   constexpr int C = 1 << LOGC;
-  const int64_t pos = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (pos >= Mpad) return;
-  const int64_t c = pos >> LOGC;
-  const int p = (int)(pos & (C - 1));
+  for (int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x; (gid >> LOGC) < nitems;
+       gid += (int64_t)gridDim.x * BS) {
+  const int64_t it = gid >> LOGC;
+  const int p = (int)(gid & (C - 1));
+  const int2 im = items[it];
+  const int64_t c = im.x, k0 = im.y;
   const int64_t base = cs[c];
   const int64_t w = (cs[c + 1] - base) >> LOGC;
+  const int64_t k1 = w < k0 + SELL_KT ? w : k0 + SELL_KT;
   const int32_t* cc = scol + base + p;
   const T* vv = sval + base + p;
-  double s0 = 0.0, s1 = 0.0;
-  int64_t k = 0;
-  for (; k + 1 < w; k += 2) {
-    const int32_t c0 = ldnt(cc + k * C), c1 = ldnt(cc + (k + 1) * C);
-    const T v0 = ldnt(vv + k * C), v1 = ldnt(vv + (k + 1) * C);
-    if (c0 >= 0) s0 += (double)v0 * (double)x[c0];
-    if (c1 >= 0) s1 += (double)v1 * (double)x[c1];
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t k = k0;
+  for (; k + 7 < k1; k += 8) {
+    int32_t c8[8];
+    T v8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c8[u] = ldnt(cc + (k + u) * C);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v8[u] = ldnt(vv + (k + u) * C);
+    issue_fence();
+    T x8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x8[u] = ld32(x, (uint32_t)(c8[u] >= 0 ? c8[u] : 0));
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sa[u & 3] += c8[u] >= 0 ? (double)v8[u] * (double)x8[u] : 0.0;
   }
-  if (k < w) {
+  for (; k < k1; ++k) {
     const int32_t c0 = ldnt(cc + k * C);
     const T v0 = ldnt(vv + k * C);
-    if (c0 >= 0) s0 += (double)v0 * (double)x[c0];
+    const T x0 = x[c0 >= 0 ? c0 : 0];
+    sa[0] += c0 >= 0 ? (double)v0 * (double)x0 : 0.0;
   }
+  const double s = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+  if (w <= SELL_KT) {
+    const int64_t pos = c * C + p;
+    const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+    if (r >= 0) y[r] = (T)s;
+  } else {
+    part[it * C + p] = s;
+  }
+  }
+}
+
+// one thread per (wide chunk, stored row): y = sum of the slices' partials in order
+template <typename T, bool PERM>
+__global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restrict__ wide,
+                           const int32_t* __restrict__ perm, const double* __restrict__ part, T* __restrict__ y) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wi = gid / C;
+  if (wi >= nwide) return;
+  const int p = (int)(gid % C);
+  const int4 wd = wide[wi];  // chunk, first item, item count
+  double s = 0.0;
+  for (int i = 0; i < wd.z; ++i) s += part[((int64_t)wd.y + i) * C + p];
+  const int64_t pos = (int64_t)wd.x * C + p;
   const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-  if (r >= 0) y[r] = (T)(s0 + s1);
+  if (r >= 0) y[r] = (T)s;
 }
 
 template <typename T, int LOGC>
 static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  const unsigned g = (unsigned)cdiv(A->Mpad, BS);
+  const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nitems << LOGC, BS), resident_blocks(8));
   if (A->perm)
-    k_sell<T, LOGC, true><<<g, BS, 0, s>>>(A->M, A->Mpad, A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x,
-                                           (T*)y);
+    k_sell<T, LOGC, true><<<g, BS, 0, s>>>(A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
+                                           (const T*)x, (T*)y, A->part);
   else
-    k_sell<T, LOGC, false><<<g, BS, 0, s>>>(A->M, A->Mpad, A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x,
-                                            (T*)y);
+    k_sell<T, LOGC, false><<<g, BS, 0, s>>>(A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
+                                            (const T*)x, (T*)y, A->part);
+  if (A->nwide > 0) {
+    const unsigned gf = (unsigned)cdiv(A->nwide << LOGC, BS);
+    if (A->perm)
+      k_sell_fix<T, true><<<gf, BS, 0, s>>>(A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
+    else
+      k_sell_fix<T, false><<<gf, BS, 0, s>>>(A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
+  }
 }
 
 template <typename T>
@@ -289,6 +412,25 @@ static spmv_status_t run_sell_t(spmv_mat_s* A, const void* x, void* y, hipStream
 spmv_status_t run_sell(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   if (A->dt == SPMV_F64) return run_sell_t<double>(A, x, y, s);
   return run_sell_t<float>(A, x, y, s);
+}
+
+// slices per chunk, and the item / wide-chunk lists
+__global__ void k_sell_nslices(int64_t nch, int C, const int64_t* cs, int32_t* ns, int32_t* wideflag) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = (cs[c + 1] - cs[c]) / C;
+    const int64_t n = w <= SELL_KT ? 1 : (w + SELL_KT - 1) / SELL_KT;
+    ns[c] = (int32_t)n;
+    wideflag[c] = n > 1;
+  }
+}
+
+__global__ void k_sell_items(int64_t nch, const int32_t* ns, const int32_t* ibase, const int32_t* wideflag,
+                             const int32_t* wpos, int2* items, int4* wide) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = ibase[c], n = ns[c];
+    for (int32_t i = 0; i < n; ++i) items[b + i] = make_int2((int)c, i * SELL_KT);
+    if (wideflag[c]) wide[wpos[c]] = make_int4((int)c, b, n, 0);
+  }
 }
 
 spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
@@ -343,9 +485,38 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
                                             A->scol, (float*)A->sval);
     SPMV_LAUNCH_CHECK();
   }
+  // work items: column slices of at most SELL_KT per chunk
+  {
+    const int64_t nch = A->nchunks;
+    DTmp ns, wf, ib, wp;
+    SPMV_TRY(ns.alloc(sizeof(int32_t) * std::max<int64_t>(nch, 1)));
+    SPMV_TRY(wf.alloc(sizeof(int32_t) * std::max<int64_t>(nch, 1)));
+    SPMV_TRY(ib.alloc(sizeof(int32_t) * (nch + 1)));
+    SPMV_TRY(wp.alloc(sizeof(int32_t) * (nch + 1)));
+    if (nch) {
+      k_sell_nslices<<<grid_rows(nch), BS, 0, s>>>(nch, C, A->cs, ns.as<int32_t>(), wf.as<int32_t>());
+      SPMV_LAUNCH_CHECK();
+    }
+    SPMV_TRY(scan_i32_to_i32(ns.as<int32_t>(), ib.as<int32_t>(), nch, s));
+    SPMV_TRY(scan_i32_to_i32(wf.as<int32_t>(), wp.as<int32_t>(), nch, s));
+    int32_t tot[1] = {0}, nw[1] = {0};
+    SPMV_TRY(copy_to_host(tot, ib.as<int32_t>() + nch, sizeof(int32_t), s));
+    SPMV_TRY(copy_to_host(nw, wp.as<int32_t>() + nch, sizeof(int32_t), s));
+    A->nitems = tot[0];
+    A->nwide = nw[0];
+    SPMV_TRY(mat_alloc(A, (void**)&A->items, sizeof(int2) * std::max<int64_t>(A->nitems, 1)));
+    SPMV_TRY(mat_alloc(A, (void**)&A->wide, sizeof(int4) * std::max<int64_t>(A->nwide, 1)));
+    if (A->nwide > 0) SPMV_TRY(mat_alloc(A, (void**)&A->part, sizeof(double) * A->nitems * C));
+    if (nch) {
+      k_sell_items<<<grid_rows(nch), BS, 0, s>>>(nch, ns.as<int32_t>(), ib.as<int32_t>(), wf.as<int32_t>(),
+                                                 wp.as<int32_t>(), A->items, A->wide);
+      SPMV_LAUNCH_CHECK();
+    }
+    SPMV_HIP(hipStreamSynchronize(s));
+  }
   A->pad_slots = A->nslots - src->nnz;
-  A->bytes_fmt = A->nslots * (4 + A->sv) + (A->nchunks + 1) * 8 + (A->perm ? A->Mpad * 4 : 0) + A->N * A->sv +
-                 A->M * A->sv;
+  A->bytes_fmt = A->nslots * (4 + A->sv) + (A->nchunks + 1) * 8 + (A->perm ? A->Mpad * 4 : 0) + A->nitems * 8 +
+                 A->N * A->sv + A->M * A->sv;
   SPMV_HIP(hipStreamSynchronize(s));
   return SPMV_OK;
 }
@@ -424,20 +595,26 @@ __global__ __launch_bounds__(BS) void k_coo(const int32_t* __restrict__ blk, con
     T vv[COO_IT];
     bool hd[COO_IT];
     uint64_t mk[COO_IT];
+    int32_t rr[COO_IT], rp[COO_IT];
 #pragma unroll
-    for (int j = 0; j < COO_IT; ++j) {
+    for (int j = 0; j < COO_IT; ++j) {  // clamped, branch-free loads at block-uniform bases
       const int k = j * BS + t;
-      hd[j] = false;
-      if (k < n) {
-        cc[j] = ldnt(ccol + c0 + k);
-        vv[j] = ldnt(cval + c0 + k);
-        hd[j] = (k == 0) || (crow[c0 + k] != crow[c0 + k - 1]);
-      }
+      const uint32_t kk = (uint32_t)(k < n ? k : n - 1);
+      cc[j] = ldnt32(ccol + c0, kk);
+      vv[j] = ldnt32(cval + c0, kk);
+      rr[j] = ld32(crow + c0, kk);
+      rp[j] = ld32(crow + c0, kk > 0 ? kk - 1 : 0u);
     }
+    issue_fence();
+    T xg[COO_IT];
+#pragma unroll
+    for (int j = 0; j < COO_IT; ++j) xg[j] = ld32(x, (uint32_t)cc[j]);
+    issue_fence();
 #pragma unroll
     for (int j = 0; j < COO_IT; ++j) {
       const int k = j * BS + t;
-      if (k < n) prod[k] = (double)vv[j] * (double)x[cc[j]];
+      hd[j] = k < n && (k == 0 || rr[j] != rp[j]);
+      if (k < n) prod[k] = (double)vv[j] * (double)xg[j];
       mk[j] = __ballot(hd[j]);
       if (__lane_id() == 0) wcnt[j * (BS / WAVE) + w] = __popcll(mk[j]);
     }

@@ -90,6 +90,19 @@ void dfree(void* p) {
   (void)hipFree(p);
 }
 
+int64_t resident_blocks(int per_cu) {
+  static int cus[64] = {0};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return (int64_t)cus[dev] * per_cu;
+}
+
 spmv_status_t copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return SPMV_OK;
   SPMV_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
