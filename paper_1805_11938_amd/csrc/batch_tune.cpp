@@ -1,0 +1,170 @@
+// Batched launch, SpMM entry point and the autotuner (host side).
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace spmv {
+spmv_status_t launch_batched(int dt, int32_t n, int64_t nitems, const void* desc, const void* const* xs,
+                             void* const* ys, int grid, hipStream_t s);
+size_t batch_desc_size();
+void batch_desc_fill(void* dst, const spmv_mat_s* A, int64_t item0);
+spmv_status_t time_run(spmv_mat_s* A, const void* x, void* y, int warmup, int min_reps, int max_reps, double rel_ci,
+                       int64_t scrub_bytes, hipStream_t s, double out[5]);
+}  // namespace spmv
+
+using namespace spmv;
+
+struct spmv_batch_s {
+  int32_t n = 0;
+  spmv_dtype_t dt = SPMV_F64;
+  int64_t nitems = 0;
+  void* desc = nullptr;   // device: n descriptors
+  void** xy = nullptr;    // device: n x pointers then n y pointers
+  std::vector<const void*> last;  // host copy of the pointers last uploaded
+};
+
+extern "C" {
+
+spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t k, spmv_stream_t s) {
+  if (!A || (A->M && (!X || !Y))) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  return run_spmm(A, X, ldx, Y, ldy, k, hs(s));
+}
+
+spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* out) {
+  if (!A || n <= 0 || !out) return fail(SPMV_ERR_INVALID_ARG, "batch arguments");
+  *out = nullptr;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!A[i] || A[i]->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_INVALID_ARG, "batch matrix %d is not CSR", i);
+    if (A[i]->dt != A[0]->dt) return fail(SPMV_ERR_INVALID_ARG, "batch mixes dtypes");
+  }
+  spmv_batch_s* b = new (std::nothrow) spmv_batch_s();
+  if (!b) return fail(SPMV_ERR_OOM, "host allocation failed");
+  b->n = n;
+  b->dt = A[0]->dt;
+  const size_t ds = batch_desc_size();
+  std::vector<char> host(ds * n);
+  int64_t items = 0;
+  for (int32_t i = 0; i < n; ++i) {  // work items: every row block of every matrix, in order
+    batch_desc_fill(host.data() + ds * i, A[i], items);
+    items += A[i]->nblk;
+  }
+  b->nitems = items;
+  spmv_status_t st = dmalloc(&b->desc, ds * n);
+  if (st == SPMV_OK) st = dmalloc((void**)&b->xy, sizeof(void*) * 2 * n);
+  if (st == SPMV_OK && hipMemcpy(b->desc, host.data(), ds * n, hipMemcpyHostToDevice) != hipSuccess)
+    st = fail(SPMV_ERR_HIP, "batch descriptor upload failed");
+  if (st != SPMV_OK) {
+    dfree(b->desc);
+    dfree(b->xy);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return SPMV_OK;
+}
+
+spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s) {
+  if (!b || !x || !y) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  std::vector<const void*> ptrs(2 * b->n);
+  for (int32_t i = 0; i < b->n; ++i) {
+    if (!x[i] || !y[i] || x[i] == y[i]) return fail(SPMV_ERR_INVALID_ARG, "bad x/y pointer for matrix %d", i);
+    ptrs[i] = x[i];
+    ptrs[b->n + i] = y[i];
+  }
+  hipStream_t st = hs(s);
+  if (ptrs != b->last) {  // upload the pointer table only when it changes
+    SPMV_HIP(hipStreamSynchronize(st));
+    SPMV_HIP(hipMemcpy(b->xy, ptrs.data(), sizeof(void*) * 2 * b->n, hipMemcpyHostToDevice));
+    b->last = ptrs;
+  }
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(b->nitems, 1), resident_blocks(6));
+  return launch_batched(b->dt, b->n, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st);
+}
+
+void spmv_batch_free(spmv_batch_t b) {
+  if (!b) return;
+  dfree(b->desc);
+  dfree(b->xy);
+  delete b;
+}
+
+// ------------------------------------------------------------ autotuner
+// Exhaustive search over a small grid per format; each candidate is
+// converted and timed with the same protocol as spmv_time (median of the
+// confidence-interval rule).  Only performance depends on the choice.
+spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void* y, int64_t scrub_bytes, int reps,
+                            spmv_params_t* inout, double* ms_out, spmv_stream_t s) {
+  if (!csr || csr->fmt != SPMV_FMT_CSR || !inout) return fail(SPMV_ERR_INVALID_ARG, "autotune arguments");
+  if (csr->M && (!y || (csr->N && !x))) return fail(SPMV_ERR_INVALID_ARG, "null x or y");
+  if (reps < 3) reps = 3;
+  hipStream_t st = hs(s);
+  spmv_params_t base;
+  resolve_params(inout, &base);
+  std::vector<spmv_params_t> cand;
+  auto add = [&](auto&& f) {
+    spmv_params_t p = base;
+    f(p);
+    cand.push_back(p);
+  };
+  switch (fmt) {
+    case SPMV_FMT_CSR:
+      add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags &= ~SPMV_FLAG_CSR_WAVES; });
+      add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags |= SPMV_FLAG_CSR_WAVES; });
+      for (int V : {4, 8, 16, 32}) add([V](spmv_params_t& p) { p.csr_lanes_per_row = V; });
+      break;
+    case SPMV_FMT_CSR5:
+      for (int sg : {4, 8, 16, 32}) add([sg](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; });
+      break;
+    case SPMV_FMT_ELL:
+      add([](spmv_params_t&) {});
+      break;
+    case SPMV_FMT_SELL:
+      for (int C : {8, 16, 32, 64})
+        for (int sg : {1, C, 8 * C, 256 * C}) add([C, sg](spmv_params_t& p) { p.sell_C = C; p.sell_sigma = sg; });
+      break;
+    case SPMV_FMT_HYB: {
+      // K from the rule, and the 50/75/90/99th percentiles of the row lengths
+      std::vector<int32_t> lens(csr->M);
+      std::vector<int32_t> hp(csr->M + 1);
+      if (csr->M) {
+        SPMV_HIP(hipMemcpyAsync(hp.data(), csr->ptr, sizeof(int32_t) * (csr->M + 1), hipMemcpyDeviceToHost, st));
+        SPMV_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < csr->M; ++i) lens[i] = hp[i + 1] - hp[i];
+        std::sort(lens.begin(), lens.end());
+      }
+      add([](spmv_params_t& p) { p.hyb_K = -1; });
+      for (double q : {0.5, 0.75, 0.9, 0.99}) {
+        const int32_t K = csr->M ? lens[(size_t)(q * (double)(csr->M - 1))] : 0;
+        add([K](spmv_params_t& p) { p.hyb_K = K; });
+      }
+      break;
+    }
+    default: return fail(SPMV_ERR_INVALID_ARG, "format %d", (int)fmt);
+  }
+  double best = 1e300;
+  spmv_params_t bestp = base;
+  bool any = false;
+  for (const spmv_params_t& p : cand) {
+    spmv_mat_t B = nullptr;
+    spmv_status_t cst = spmv_convert(csr, fmt, &p, s, &B);
+    if (cst == SPMV_ERR_TOO_LARGE || cst == SPMV_ERR_UNSUPPORTED) continue;
+    if (cst != SPMV_OK) return cst;
+    double out[5];
+    spmv_status_t tst = time_run(B, x, y, 2, reps, reps, 0.0, scrub_bytes, st, out);
+    const spmv_params_t used = B->params;
+    spmv_mat_free(B);
+    if (tst != SPMV_OK) return tst;
+    if (out[0] < best) {
+      best = out[0];
+      bestp = used;
+      any = true;
+    }
+  }
+  if (!any) return fail(SPMV_ERR_TOO_LARGE, "no candidate of format %d fits the byte cap", (int)fmt);
+  *inout = bestp;
+  if (ms_out) *ms_out = best;
+  return SPMV_OK;
+}
+
+}  // extern "C"

@@ -420,6 +420,84 @@ spmv_status_t run_csr(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   return run_csr_t<float>(A, (const float*)x, (float*)y, s);
 }
 
+// ----------------------------------------------------------------- SpMM
+// Y = A X for k right-hand sides (row-major, k <= 64).  Same row blocks as
+// the SpMV kernel; the block's col/val are staged in LDS once and reused by
+// all k columns.  Thread t works on column c = t % k of rows t / k,
+// t / k + G, ... (G = 256 / k): the k threads of a row read k consecutive
+// values of X per nonzero and write k consecutive values of Y.
+constexpr int SPMM_CAP = 2048;
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __restrict__ blk_row,
+                                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                 const T* __restrict__ val, const T* __restrict__ X, int64_t ldx,
+                                                 T* __restrict__ Y, int64_t ldy, int k) {
+  __shared__ int32_t scol[SPMM_CAP];
+  __shared__ T sval[SPMM_CAP];
+  __shared__ double red[BS];
+  const int t = threadIdx.x;
+  const int G = BS / k;
+  const int g = t / k, c = t % k;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t r0 = blk_row[b], r1 = blk_row[b + 1];
+    if (r0 >= r1) continue;
+    const int64_t k0 = ptr[r0], E = ptr[r1] - k0;
+    if (E <= SPMM_CAP) {
+      for (int64_t q = t; q < E; q += BS) {
+        scol[q] = ldnt(col + k0 + q);
+        sval[q] = ldnt(val + k0 + q);
+      }
+      __syncthreads();
+      if (g < G)
+        for (int64_t r = r0 + g; r < r1; r += G) {
+          const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
+          double s0 = 0.0, s1 = 0.0;
+          int q = a;
+          for (; q + 1 < e; q += 2) {
+            s0 += (double)sval[q] * (double)X[(int64_t)scol[q] * ldx + c];
+            s1 += (double)sval[q + 1] * (double)X[(int64_t)scol[q + 1] * ldx + c];
+          }
+          if (q < e) s0 += (double)sval[q] * (double)X[(int64_t)scol[q] * ldx + c];
+          Y[r * ldy + c] = (T)(s0 + s1);
+        }
+      __syncthreads();
+    } else {
+      // rows one at a time: G groups stride over the row's nonzeros, then an
+      // ordered sum of the groups' partials in LDS
+      for (int64_t r = r0; r < r1; ++r) {
+        const int64_t a = ptr[r], e = ptr[r + 1];
+        double s = 0.0;
+        if (g < G)
+          for (int64_t q = a + g; q < e; q += G) s += (double)ldnt(val + q) * (double)X[(int64_t)ldnt(col + q) * ldx + c];
+        red[t] = s;
+        __syncthreads();
+        if (g == 0) {
+          double tot = 0.0;
+          for (int gg = 0; gg < G; ++gg) tot += red[gg * k + c];
+          Y[r * ldy + c] = (T)tot;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {
+  if (A->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_UNSUPPORTED, "spmm runs on CSR handles");
+  if (k < 1 || k > 64 || ldx < k || ldy < k) return fail(SPMV_ERR_INVALID_ARG, "spmm needs 1 <= k <= 64, ld >= k");
+  if (A->M == 0) return SPMV_OK;
+  const unsigned g = (unsigned)std::min<int64_t>(A->nblk, resident_blocks(4));
+  if (A->dt == SPMV_F64)
+    k_csr_spmm<double><<<g, BS, 0, s>>>(A->nblk, A->blk_row, A->ptr, A->col, (const double*)A->val,
+                                        (const double*)X, ldx, (double*)Y, ldy, k);
+  else
+    k_csr_spmm<float><<<g, BS, 0, s>>>(A->nblk, A->blk_row, A->ptr, A->col, (const float*)A->val, (const float*)X,
+                                       ldx, (float*)Y, ldy, k);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
+}
+
 // ------------------------------------------------------- batched launch
 // A work item is one row block of one matrix; items are numbered across
 // the batch (prefix of row-block counts), so the list is balanced by

@@ -1,0 +1,96 @@
+"""GPU parity of the multi-RHS SpMM, the batched persistent launch and the
+autotuner's choices, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_11938_amd import synth
+from paper_1805_11938_amd import spmv as S
+
+from gpu_util import TOL, device_vec, reference, rowwise_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+SPMM_MATS = [("stencil27_12", synth.stencil27(12)), ("zipf_long", synth.zipf_rows(8000, 8000, 2.0, 16, 6000, 4, 5)),
+             ("empty_rows", synth.uniform_random(5000, 7000, 1.0, 3, 4)), ("laplace", synth.laplace2d(32))]
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 16, 64])
+@pytest.mark.parametrize("mi", range(len(SPMM_MATS)), ids=[m[0] for m in SPMM_MATS])
+def test_spmm_matches_oracle(torch, mi, k):
+    name, A = SPMM_MATS[mi]
+    X = synth.uniform(A.N * k, 9 + k, -1.0, 1.0).reshape(A.N, k)
+    Yref = oracle.csr_spmm(A.M, A.ptr, A.col, A.val, X)
+    den = np.stack([oracle.csr_absspmv(A.M, A.ptr, A.col, A.val, X[:, c]) for c in range(k)], axis=1)
+    Ad = S.Matrix.from_host(A)
+    Y = Ad.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(k):
+        assert rowwise_err(Y[:, c], Yref[:, c], den[:, c]) <= TOL[0], (name, k, c)
+    # padded leading dimensions
+    Xp = np.zeros((A.N, k + 5))
+    Xp[:, :k] = X
+    Yp = torch.full((A.M, k + 3), float("nan"), dtype=torch.float64, device="cuda")
+    Xd = torch.from_numpy(Xp).cuda()
+    S.check(S.lib().spmv_spmm(Ad.h, S.dptr(Xd), k + 5, S.dptr(Yp), k + 3, k, S.stream()))
+    Ypn = Yp.cpu().numpy()
+    assert np.all(np.isnan(Ypn[:, k:]))  # columns past k untouched
+    for c in range(k):
+        assert rowwise_err(Ypn[:, c], Yref[:, c], den[:, c]) <= TOL[0]
+
+
+def test_spmm_integer_exact(torch):
+    A = synth.random_pattern(900, 700, 0.02, 7, integer_values=True)
+    X = np.round(synth.uniform(700 * 8, 3, -8, 8)).reshape(700, 8)
+    Y = S.Matrix.from_host(A).spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.array_equal(Y, oracle.csr_spmm(A.M, A.ptr, A.col, A.val, X))
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+def test_batched_matches_per_matrix_oracle(torch, dt):
+    specs = synth.batch_specs(24, seed=8, rows_lo=200, rows_hi=20_000)
+    mats = [synth.make(s) for s in specs]
+    mats.append(synth.zipf_rows(3000, 3000, 2.0, 16, 3000, 1, 2))  # long rows inside the batch
+    mats.append(synth.from_dense(np.zeros((17, 5))))  # all-empty matrix
+    handles, xs, ys, refs = [], [], [], []
+    for i, A in enumerate(mats):
+        val = A.val.astype(np.float32) if dt == 1 else A.val
+        handles.append(S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt))
+        x64 = synth.vector(A.N, 50 + i)
+        if dt == 1:
+            x64 = x64.astype(np.float32).astype(np.float64)
+        xs.append(device_vec(x64, dt))
+        ys.append(torch.full((A.M,), float("nan"), dtype=S.torch_dtype(dt), device="cuda"))
+        refs.append(reference(A, x64, dt))
+    B = S.Batch(handles)
+    for rep in range(2):  # second run reuses the uploaded pointer table
+        B.run(xs, ys)
+        torch.cuda.synchronize()
+        for y, (yref, den) in zip(ys, refs):
+            assert rowwise_err(y.cpu().numpy().astype(np.float64), yref, den) <= TOL[dt]
+
+
+@pytest.mark.parametrize("fmt", ["csr", "csr5", "ell", "sell", "hyb"])
+def test_autotune_picks_a_valid_configuration(torch, fmt):
+    A = synth.zipf_rows(60_000, 60_000, 2.0, 12, 2000, 6, 7)
+    x64 = synth.vector(A.N, 2)
+    yref, den = reference(A, x64, 0)
+    Ad = S.Matrix.from_host(A)
+    x = device_vec(x64, 0)
+    y = torch.empty(A.M, dtype=torch.float64, device="cuda")
+    p, ms = Ad.autotune(fmt, x, y, scrub_bytes=64 << 20, reps=5)
+    assert ms > 0
+    B = Ad.convert(fmt, **{k: v for k, v in p.items()})
+    out = B.run(x).cpu().numpy()
+    assert rowwise_err(out, yref, den) <= TOL[0]
+    if fmt == "sell":
+        assert p["sell_C"] in (8, 16, 32, 64)
+    if fmt == "csr5":
+        assert p["csr5_sigma"] in (4, 8, 16, 32)
