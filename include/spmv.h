@@ -216,6 +216,9 @@ spmv_status_t spmv_mlp_adam(float* params, const float* grads, float* m, float* 
  * features) -> X (n x 12 FP32 scaled).  fmin/fmax: host arrays. */
 spmv_status_t spmv_scale_features(const double* F, int32_t n, const double fmin[12], const double fmax[12],
                                   float* X, spmv_stream_t s);
+/* Scaler fit: per-feature minimum and maximum of the transformed features
+ * of F (n x 12 FP64 raw features, device), returned to the host. */
+spmv_status_t spmv_feature_range(const double* F, int32_t n, double fmin[12], double fmax[12], spmv_stream_t s);
 /* Whole training run: epochs x (n / batch) Adam steps over device data X
  * (n x 12 scaled), labels (n); order (epochs x n int32, device) gives the
  * sample order of every epoch; the last partial batch is used as is.

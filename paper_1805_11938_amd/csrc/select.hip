@@ -305,6 +305,22 @@ __global__ void k_scale(const double* __restrict__ F, int32_t n, const double* _
   X[q] = span > 0.0 ? (float)((t - lo[k]) / span) : 0.0f;
 }
 
+// per-feature minimum and maximum of the transformed features (one thread
+// per feature, rows in order)
+__global__ void k_feat_range(const double* __restrict__ F, int32_t n, double* __restrict__ lo,
+                             double* __restrict__ hi) {
+  const int k = threadIdx.x;
+  if (k >= NIN) return;
+  double a = 1e308, b = -1e308;
+  for (int32_t i = 0; i < n; ++i) {
+    const double t = feat_transform(k, F[(int64_t)i * NIN + k]);
+    a = t < a ? t : a;
+    b = t > b ? t : b;
+  }
+  lo[k] = a;
+  hi[k] = b;
+}
+
 // single-sample inference: scale, forward, argmax (ties -> lower index)
 __global__ void k_select(const float* __restrict__ P, const double* __restrict__ F, const double* __restrict__ lo,
                          const double* __restrict__ hi, int32_t* __restrict__ best, float* __restrict__ scores) {
@@ -421,6 +437,19 @@ spmv_status_t spmv_scale_features(const double* F, int32_t n, const double fmin[
   k_scale<<<(unsigned)cdiv((int64_t)n * NIN, BS), BS, 0, hs(s)>>>(F, n, lo.as<double>(), hi.as<double>(), X);
   SPMV_LAUNCH_CHECK();
   SPMV_HIP(hipStreamSynchronize(hs(s)));
+  return SPMV_OK;
+}
+
+spmv_status_t spmv_feature_range(const double* F, int32_t n, double fmin[12], double fmax[12], spmv_stream_t s) {
+  if (!F || n <= 0 || !fmin || !fmax) return fail(SPMV_ERR_INVALID_ARG, "feature range arguments");
+  DTmp r;
+  SPMV_TRY(r.alloc(24 * sizeof(double)));
+  k_feat_range<<<1, WAVE, 0, hs(s)>>>(F, n, r.as<double>(), r.as<double>() + 12);
+  SPMV_LAUNCH_CHECK();
+  double h[24];
+  SPMV_TRY(copy_to_host(h, r.p, sizeof(h), hs(s)));
+  memcpy(fmin, h, 12 * sizeof(double));
+  memcpy(fmax, h + 12, 12 * sizeof(double));
   return SPMV_OK;
 }
 

@@ -60,7 +60,7 @@ EXPORTED = [
     "spmv_batch_create", "spmv_batch_run", "spmv_batch_free", "spmv_time", "spmv_scrub", "spmv_copy_probe",
     "spmv_autotune", "spmv_features", "spmv_model_create", "spmv_model_load", "spmv_model_save",
     "spmv_model_params", "spmv_model_free", "spmv_select", "spmv_mlp_forward", "spmv_mlp_backward", "spmv_mlp_adam",
-    "spmv_scale_features", "spmv_mlp_train",
+    "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train",
 ]
 
 _L = None
@@ -106,6 +106,7 @@ def lib():
             "spmv_mlp_adam": (st, [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, vp]),
             "spmv_scale_features": (st, [vp, i32, vp, vp, vp, vp]),
+            "spmv_feature_range": (st, [vp, i32, vp, vp, vp]),
             "spmv_mlp_train": (st, [vp, vp, vp, i32, vp, i32, i32, ctypes.c_float, vp, vp]),
         }
         for name, (res, args) in sig.items():
