@@ -1,0 +1,76 @@
+"""Host logic of the selector driver: labels, metrics and the split.
+
+These run without a GPU; the metric definitions are checked on tables whose
+answers are worked out by hand."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1805_11938_amd import selector as SEL
+
+INF = math.inf
+
+
+def test_label_is_argmin_with_low_index_ties():
+    assert SEL.label_of([3, 2, 2, 5, 9]) == 1
+    assert SEL.label_of([INF, INF, 7, INF, 7]) == 2
+    assert SEL.label_of([1, 1, 1, 1, 1]) == 0
+
+
+def test_evaluate_hand_worked_table():
+    # two matrices; best times 1 and 1
+    T = [[1.0, 2.0, 4.0, 1.0, 8.0],
+         [2.0, 1.0, INF, 4.0, 2.0]]
+    r = SEL.evaluate(T, [3, 4])
+    # t_best/t_pred = 1/1 and 1/2
+    assert r["frac"] == pytest.approx(0.75)
+    assert r["geo"] == pytest.approx(math.sqrt(0.5))
+    assert r["accuracy"] == 0.0  # labels are 0 (tie goes to csr) and 1
+    assert r["best_counts"] == {"csr": 1, "csr5": 1, "ell": 0, "sell": 0, "hyb": 0}
+    f = r["fixed"]
+    assert f["csr"]["frac"] == pytest.approx((1 + 0.5) / 2)
+    assert f["csr5"]["frac"] == pytest.approx((0.5 + 1) / 2)
+    # infeasible ELL counts as 0 in the arithmetic mean and is left out of
+    # the slowdown and the geometric mean
+    assert f["ell"]["frac"] == pytest.approx(0.25 / 2)
+    assert f["ell"]["infeasible"] == 1
+    assert f["ell"]["slowdown"] == pytest.approx(4.0)
+    assert f["ell"]["geo"] == pytest.approx(0.25)
+    assert f["hyb"]["slowdown"] == pytest.approx((8 + 2) / 2)
+    assert r["best_fixed"] in ("csr", "csr5")
+
+
+def test_evaluate_perfect_prediction_is_one():
+    rng = np.random.default_rng(0)
+    T = rng.uniform(1, 10, (50, 5))
+    T[rng.random((50, 5)) < 0.1] = INF
+    T[:, 0] = np.minimum(T[:, 0], 10)  # at least one feasible format per row
+    pred = [SEL.label_of(t) for t in T]
+    r = SEL.evaluate(T, pred)
+    assert r["frac"] == 1.0 and r["accuracy"] == 1.0 and r["geo"] == 1.0
+
+
+def _records(n_per_kind, kinds=("banded", "blockdiag", "uniform", "zipf", "rmat")):
+    out = []
+    i = 0
+    for k in kinds:
+        for _ in range(n_per_kind):
+            for dt in ("f64", "f32"):
+                out.append(dict(index=i, kind=k, dtype=dt))
+            i += 1
+    return out
+
+
+def test_split_is_stratified_seeded_and_dtype_consistent():
+    recs = _records(100)
+    a = SEL.split(recs, 0.2, seed=7)
+    b = SEL.split(recs, 0.2, seed=7)
+    c = SEL.split(recs, 0.2, seed=8)
+    assert a == b and a != c
+    assert len(a) == 100  # 20% of 500 matrices
+    for k in ("banded", "blockdiag", "uniform", "zipf", "rmat"):
+        idx = {r["index"] for r in recs if r["kind"] == k}
+        assert len(idx & a) == 20
+    # the split is over matrices, so both dtypes of a matrix share a side
+    assert all(isinstance(i, int) for i in a)
