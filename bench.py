@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
-"""SpMV benchmark on one MI355X: every storage format on the two 1M-row FP64
+"""SpMV benchmark on one MI355X: every storage format on the two 1M-row
 workloads (3-D 27-point stencil on 100^3, 26,463,592 nnz; 1M x 1M with
-Zipf(2) row lengths, mean 16, max 10^4, ~16M nnz).
+Zipf(2) row lengths, mean 16, max 10^4, ~16M nnz), FP64 by default.
 
 A step is one pass of the hot path over that batch: y = A x once per
-(matrix, format) pair, each launch preceded by a cache scrub (512 MB, so
-neither L2 nor the 256 MB Infinity Cache holds the matrix) and bracketed by
-HIP events on the launch stream.  ELL of the Zipf matrix needs 120 GB and is
-refused by the library's default 64 GB cap, so a step has 9 launches.
+(matrix, format) pair, in the autotuned launch configuration, each launch
+preceded by a cache scrub (512 MB, so neither L2 nor the 256 MB Infinity
+Cache holds the matrix) and bracketed by HIP events on the launch stream.
+ELL of the Zipf matrix needs 120 GB and is refused by the library's default
+64 GB cap, so a step has 9 launches.
 
 Prints one JSON line.  `value` = algorithmic bytes of all launches of the
-timed steps / their summed event time (GB/s); per-format figures are in
-`per_format`; `roofline` describes the launch with the largest time share;
+timed steps / their summed event time (GB/s); per-format figures (GB/s,
+GFLOP/s, roofline fraction, one-off conversion time) are in `per_format`;
+`roofline` describes the launch with the largest time share; `selector`
+gives the learned model's choice per matrix against the measured best;
 `cpu_baseline` times the FP64 CSR oracle on the host cores on the same two
-matrices.
+matrices.  `--workload rmat24` measures the R-MAT scale-24 matrix instead
+(CSR, CSR5, SELL, HYB).
 """
 from __future__ import annotations
 
@@ -30,50 +34,75 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 SCRUB = 512 << 20
-FORMATS = [("csr", {}), ("csr5", {}), ("ell", {}), ("sell", {"sell_C": 32, "sell_sigma": 1}), ("hyb", {})]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def load_tuned():
-    """Tuned parameters per workload, written by the autotuner run (optional)."""
-    p = os.path.join(ROOT, "paper_1805_11938_amd", "tuned_params.json")
-    if os.path.exists(p):
-        return json.load(open(p))
-    return {}
+def build_workload(names):
+    from paper_1805_11938_amd import workloads as W
+    out = []
+    for name in names:
+        t0 = time.time()
+        A = W.make(name)
+        out.append((name, A, W.x_vector(name, A.N)))
+        log(f"[bench] generated {name} in {time.time() - t0:.1f}s")
+    return out
 
 
-def build_workload():
-    from paper_1805_11938_amd import synth
-    t0 = time.time()
-    a = synth.stencil27(100, seed=2)
-    xa = synth.vector(a.N, 3)
-    b = synth.zipf_rows(1_000_000, 1_000_000, 2.0, 16.0, 10_000, seed=4, val_seed=5)
-    xb = synth.vector(b.N, 6)
-    log(f"[bench] generated workloads in {time.time() - t0:.1f}s: stencil27 nnz={a.nnz}, zipf nnz={b.nnz}")
-    return [("stencil27_100", a, xa), ("zipf_1M", b, xb)]
-
-
-def cpu_baseline(work, budget_s=15.0):
-    """The oracle's FP64 CSR loop, OpenMP rows over the host cores."""
+def cpu_baseline(work, sv, budget_s=15.0):
+    """The oracle's FP64 CSR loop, OpenMP rows over the host cores (FP32
+    values are promoted, so its bytes are counted at the FP64 size)."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
-    tot_bytes, tot_t, reps = 0.0, 0.0, 0
+    tot_bytes, tot_t, reps, used = 0.0, 0.0, 0, 1
     t_start = time.time()
     while time.time() - t_start < budget_s or reps < 2:
-        for name, A, x in work:
+        for name, M, ptr, col, val, x in work:
             t0 = time.perf_counter()
-            _, used = oracle.csr_spmv_omp(A.M, A.ptr, A.col, A.val, x, threads)
+            _, used = oracle.csr_spmv_omp(M, ptr, col, val, x, threads)
             tot_t += time.perf_counter() - t0
-            tot_bytes += A.nnz * 12 + 4 * (A.M + 1) + 8 * A.N + 8 * A.M
+            tot_bytes += len(col) * 12 + 4 * (M + 1) + 8 * len(x) + 8 * M
         reps += 1
         if reps >= 20000:
             break
     return {"value": round(tot_bytes / tot_t / 1e9, 3), "unit": "GB/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{reps} passes of y=Ax over both full matrices (FP64 CSR loop, OpenMP static rows)",
+            "sample": f"{reps} passes of y=Ax over every matrix of the workload in full (FP64 CSR loop, "
+                      f"OpenMP static rows), about {budget_s:.0f} s",
             "ms_per_step": round(1e3 * tot_t / reps, 3)}
+
+
+WORKLOADS = {"c2": ("stencil27_100", "zipf_1M"), "rmat24": ("rmat24",)}
+DESCR = {"c2": "27-pt stencil 100^3 (26.46M nnz) + Zipf(2) 1Mx1M (16M nnz), int32 indices, all formats",
+         "rmat24": "R-MAT(0.57,0.19,0.19) scale 24, 2^28 edge draws (~2.6e8 nnz after duplicate sums), int32 "
+                   "indices, CSR/CSR5/SELL/HYB"}
+
+
+def selector_choices(bases, per, dname):
+    """The learned model's pick per matrix, judged by this run's times."""
+    from paper_1805_11938_amd import selector as SEL
+    from paper_1805_11938_amd import spmv as S
+    path = SEL.model_path(dname)
+    if not os.path.exists(path):
+        return None
+    model = S.Model.load(path)
+    out = {}
+    for name, base in bases.items():
+        fmt, _ = SEL.choose(base, model)
+        t = {f: per[f"{name}/{f}"]["ms"] for f in S.FMT_NAMES if f"{name}/{f}" in per}
+        best = min(t, key=t.get)
+        out[name] = {"chosen": fmt, "best": best, "frac_of_best": round(t[best] / t[fmt], 4) if fmt in t else 0.0,
+                     "csr_frac_of_best": round(t[best] / t["csr"], 4)}
+    rep = os.path.join(SEL.DATA_DIR, "selector_report.json")
+    if os.path.exists(rep):
+        r = json.load(open(rep)).get(dname)
+        if r and "test" in r:
+            out["held_out"] = {"n": r["test"]["n"], "frac_of_best": round(r["test"]["frac"], 4),
+                               "fixed_csr_frac": round(r["test"]["fixed"]["csr"]["frac"], 4),
+                               "best_fixed": r["test"]["best_fixed"],
+                               "best_fixed_frac": round(r["test"]["fixed"][r["test"]["best_fixed"]]["frac"], 4)}
+    return out
 
 
 def main():
@@ -81,6 +110,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated matrix/format labels to run (default: all)")
     ap.add_argument("--warm", action="store_true", help="skip the cache scrub between launches (labelled warm)")
@@ -89,40 +120,63 @@ def main():
                     help="measured HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE), if present")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
-              f"design note, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU row sharding "
+              f"is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1805_11938_amd import spmv as S
+    from paper_1805_11938_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
-    work = build_workload()
-    tuned = load_tuned()
+    dt = S.F64 if args.dtype == "f64" else S.F32
+    tdt = torch.float64 if dt == S.F64 else torch.float32
+    sv = 8 if dt == S.F64 else 4
+    work = build_workload(WORKLOADS[args.workload])
+    formats = ("csr", "csr5", "sell", "hyb") if args.workload == "rmat24" else W.FORMATS
 
-    launches = []  # (label, matrix handle, x, y, bytes_fmt, nnz)
+    launches = []  # dicts: label, matrix handle, x, y, algorithmic bytes, nnz, params, conversion time
+    bases = {}
+    cpu_work = []
     t0 = time.time()
+    stream = torch.cuda.current_stream()
     for name, A, x64 in work:
-        base = S.Matrix.from_host(A, S.F64)
-        x = torch.from_numpy(x64).to(dev)
-        y = torch.empty(A.M, dtype=torch.float64, device=dev)
-        for fmt, kw in FORMATS:
-            kw = dict(kw, **tuned.get(name, {}).get(fmt, {}))
+        if isinstance(A, synth_coo_type()):
+            val = A.val.astype(np.float32) if dt == S.F32 else A.val
+            base = S.Matrix.from_coo(A.M, A.N, A.row, A.col, val, dt)
+        else:
+            val = A.val.astype(np.float32) if dt == S.F32 else A.val
+            base = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt)
+        x = torch.from_numpy(x64).to(dev, tdt)
+        y = torch.empty(A.M, dtype=tdt, device=dev)
+        for fmt in formats:
+            label = f"{name}/{fmt}"
+            if args.only and label not in args.only.split(","):
+                continue
+            kw = W.tuned_params(name, fmt, args.dtype)
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
             try:
+                c0.record(stream)
                 B = base.convert(fmt, **kw)
+                c1.record(stream)
+                torch.cuda.synchronize()
             except S.SpmvError as e:
-                log(f"[bench] {name}/{fmt}: not built ({e})")
+                log(f"[bench] {label}: not built ({e})")
                 continue
-            if args.only and f"{name}/{fmt}" not in args.only.split(","):
-                continue
-            launches.append(dict(label=f"{name}/{fmt}", m=B, x=x, y=y, bytes=B.info.bytes_fmt,
-                                 bytes_min=B.info.bytes_min, nnz=A.nnz, params=B.params))
-        del base
+            launches.append(dict(label=label, m=B, x=x, y=y, bytes=B.info.bytes_fmt, bytes_min=B.info.bytes_min,
+                                 nnz=base.nnz, params=B.params, convert_ms=c0.elapsed_time(c1)))
+        bases[name] = base
+        if not args.no_cpu:
+            if isinstance(A, synth_coo_type()):
+                ptr, col, v = base.to_csr()  # the oracle is timed on the canonical CSR
+                cpu_work.append((name, base.M, ptr, col, v.astype(np.float64), x64))
+            else:
+                cpu_work.append((name, A.M, A.ptr, A.col, A.val, x64))
+    del work
     torch.cuda.synchronize()
     log(f"[bench] converted {len(launches)} (matrix, format) pairs in {time.time() - t0:.1f}s")
-
-    stream = torch.cuda.current_stream()
 
     def step(record):
         for L in launches:
@@ -139,6 +193,7 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    log(f"[bench] warmup done; timing {args.steps} steps")
     t_wall = time.perf_counter()
     for _ in range(args.steps):
         step(True)
@@ -155,7 +210,8 @@ def main():
                            "GBps": round(gbps, 1), "eff_GBps": round(L["bytes_min"] / (t * 1e-3) / 1e9, 1),
                            "GFLOPs": round(2 * L["nnz"] / (t * 1e-3) / 1e9, 1),
                            "frac_hbm": round(gbps / HBM_PEAK_GBPS, 4), "bytes": int(L["bytes"]),
-                           "params": {k: v for k, v in L["params"].items() if k != "flags"}}
+                           "convert_ms": round(L["convert_ms"], 3),
+                           "params": {k: v for k, v in L["params"].items() if k != "max_bytes"}}
         tot_b += L["bytes"] * len(ts)
         tot_t += sum(ts) * 1e-3
     value = tot_b / tot_t / 1e9
@@ -163,28 +219,35 @@ def main():
     dper = per[dom["label"]]
     traffic = None
     if os.path.exists(args.traffic):
-        tr = json.load(open(args.traffic)).get(dom["label"])
-        if tr:
+        tr = json.load(open(args.traffic)).get(f"{args.dtype}:{dom['label']}")
+        if tr and tr.get("params") == dper["params"]:
             traffic = tr.get("bytes_per_launch")
     roof = {"bound": "hbm", "achieved": dper["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(dper["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom["label"],
-            "bytes_per_launch": int(dom["bytes"])}
+            "bytes_per_launch": int(dom["bytes"]), "ms_per_launch": dper["ms"]}
     out = {"metric": "SpMV GB/s & % HBM roofline per format; selector % of best-format throughput vs CSR",
            "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1e3 * wall / args.steps, 4),
            "spmv_ms_per_step": round(1e3 * tot_t / args.steps, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
            "data": "synthetic (seeded generators)",
-           "config": {"workload": "27-pt stencil 100^3 (26.46M nnz) + Zipf(2) 1Mx1M (16M nnz), FP64, int32 "
-                                  "indices, all formats, " + ("warm cache" if args.warm else "cold cache"),
+           "config": {"workload": DESCR[args.workload] + ", " + ("warm cache" if args.warm else "cold cache"),
                       "launches_per_step": len(launches)},
            "roofline": roof, "per_format": per}
+    sel = selector_choices(bases, per, args.dtype)
+    if sel is not None:
+        out["selector"] = sel
     if args.copy_probe:
         out["copy_probe_GBps"] = round(S.copy_probe(1 << 30, 20), 1)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(work)
+        out["cpu_baseline"] = cpu_baseline(cpu_work, sv)
     print(json.dumps(out), flush=True)
+
+
+def synth_coo_type():
+    from paper_1805_11938_amd import synth
+    return synth.HostCOO
 
 
 if __name__ == "__main__":

@@ -1,0 +1,130 @@
+"""Summaries of rocprofv3 output for the benchmark's launches.
+
+Two uses:
+
+* ``stats``: per-kernel call counts and average durations from a
+  ``--kernel-trace --stats`` run (``*_kernel_stats.csv``), as text.
+* ``traffic``: HBM bytes per benchmark launch from two counter runs
+  (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``; both counters are KiB per
+  dispatch).  The benchmark scrubs the caches before every launch, so the
+  dispatches between two scrub kernels belong to one (matrix, format)
+  launch, in the order the benchmark prints.  The counters are calibrated
+  on a kernel whose traffic is known: the 1 GiB copy probe (1 GiB read,
+  1 GiB written; ``bench.py --copy-probe``).
+
+    python -m paper_1805_11938_amd.profiling stats DIR/..._kernel_stats.csv
+    python -m paper_1805_11938_amd.profiling traffic FETCH.csv WRITE.csv BENCH.json OUT.json
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import json
+import sys
+
+SCRUB = "k_scrub"
+COPY = "k_copy"
+# kernels that spmv_run launches (conversion, feature and selection kernels
+# run outside the scrubbed launches and are not counted)
+RUN_KERNELS = ("k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_ell", "k_ell2",
+               "k_sell", "k_sell_fix", "k_coo")
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def stats(path: str, top: int = 40) -> str:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"{'kernel':70s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_%':>8s}"]
+    for r in rows[:top]:
+        out.append(f"{_short(r['Name'])[:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):8.2f}")
+    return "\n".join(out)
+
+
+def _per_dispatch(path: str, counter: str):
+    """[(dispatch id, kernel, value in bytes)] in dispatch order."""
+    vals = collections.OrderedDict()
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        k = _short(r["Kernel_Name"])
+        v = float(r["Counter_Value"]) * 1024.0
+        if d in vals:
+            vals[d] = (k, vals[d][1] + v)
+        else:
+            vals[d] = (k, v)
+    return [(d, k, v) for d, (k, v) in sorted(vals.items())]
+
+
+def _segments(disp):
+    """Groups of consecutive dispatches that follow a scrub kernel."""
+    segs, cur = [], None
+    for d, k, v in disp:
+        if SCRUB in k:
+            if cur:
+                segs.append(cur)
+            cur = []
+        elif cur is not None and k.split("<")[0] in RUN_KERNELS:
+            cur.append((k, v))
+    if cur:
+        segs.append(cur)
+    return segs
+
+
+def _calibration(disp):
+    copy = [v for _, k, v in disp if COPY in k]
+    if not copy:
+        raise ValueError("no copy-probe dispatches: run the benchmark with --copy-probe")
+    return float(sum(copy) / len(copy)), float(1 << 30), COPY
+
+
+def traffic(fetch_csv: str, write_csv: str, bench_json: str, out_json: str):
+    bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    labels = list(bench["per_format"].keys())
+    dt = bench["dtype"]
+    F = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    Wr = _per_dispatch(write_csv, "WRITE_SIZE")
+    fm, fk, fsrc = _calibration(F)
+    wm, wk, wsrc = _calibration(Wr)
+    ff, wf = fk / fm, wk / wm
+    sf, sw = _segments(F), _segments(Wr)
+    n = len(labels)
+    if len(sf) < n or len(sf) % n or len(sw) != len(sf):
+        raise ValueError(f"{len(sf)} launches in the FETCH run, {len(sw)} in the WRITE run, {n} labels")
+    res = {"_calibration": {"fetch_factor": ff, "write_factor": wf, "kernel": fsrc,
+                            "fetch_raw_bytes": fm, "write_raw_bytes": wm, "known_bytes": fk}}
+    for i, lab in enumerate(labels):
+        fb = [sum(v for _, v in sf[j]) for j in range(i, len(sf), n)]
+        wb = [sum(v for _, v in sw[j]) for j in range(i, len(sw), n)]
+        fetch = ff * sum(fb) / len(fb)
+        write = wf * sum(wb) / len(wb)
+        alg = bench["per_format"][lab]["bytes"]
+        res[f"{dt}:{lab}"] = {"bytes_per_launch": int(round(fetch + write)), "fetch_bytes": int(round(fetch)),
+                              "write_bytes": int(round(write)), "algorithmic_bytes": alg,
+                              "ratio": round((fetch + write) / alg, 4),
+                              "kernels": [k for k, _ in sf[i]], "params": bench["per_format"][lab]["params"]}
+    json.dump(res, open(out_json, "w"), indent=1)
+    return res
+
+
+def main(argv):
+    if argv[0] == "stats":
+        print(stats(argv[1]))
+    elif argv[0] == "traffic":
+        r = traffic(*argv[1:5])
+        for k, v in r.items():
+            if k.startswith("_"):
+                print(k, v)
+            else:
+                print(f"{k:40s} measured {v['bytes_per_launch'] / 1e6:10.1f} MB  algorithmic "
+                      f"{v['algorithmic_bytes'] / 1e6:10.1f} MB  ratio {v['ratio']:.3f}")
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -281,6 +281,27 @@ def exhaustive(Ad, x, y):
     return CLASSES[f], params[CLASSES[f]], times
 
 
+def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB):
+    """Pick a format and its parameters for a CSR handle and return the
+    converted handle with how it was chosen.
+
+    With a model: predicted format, then (tune=True) the autotuner's
+    parameters for it.  Without a model, or when the model's top softmax
+    probability beats the runner-up by less than `margin`, every format is
+    profiled and the fastest is taken (the exhaustive fallback)."""
+    if model is not None:
+        fmt, z = choose(Ad, model)
+        p = np.exp(z - z.max())
+        p = np.sort(p / p.sum())[::-1]
+        if p[0] - p[1] >= margin:
+            params = {}
+            if tune:
+                params, _ = Ad.autotune(fmt, x, y, scrub_bytes=scrub, reps=3)
+            return Ad.convert(fmt, **params), fmt, "model"
+    fmt, params, _ = exhaustive(Ad, x, y)
+    return Ad.convert(fmt, **(params or {})), fmt, "exhaustive"
+
+
 # ---------------------------------------------------------------- CLI
 
 def main(argv=None):
