@@ -90,10 +90,15 @@ def selector_choices(bases, per, dname):
     out = {}
     for name, base in bases.items():
         fmt, _ = SEL.choose(base, model)
+        w0 = time.perf_counter()
+        for _ in range(10):  # features + inference, both synchronous
+            SEL.choose(base, model)
+        ov = (time.perf_counter() - w0) / 10 * 1e3
         t = {f: per[f"{name}/{f}"]["ms"] for f in S.FMT_NAMES if f"{name}/{f}" in per}
         best = min(t, key=t.get)
         out[name] = {"chosen": fmt, "best": best, "frac_of_best": round(t[best] / t[fmt], 4) if fmt in t else 0.0,
-                     "csr_frac_of_best": round(t[best] / t["csr"], 4)}
+                     "csr_frac_of_best": round(t[best] / t["csr"], 4), "overhead_ms": round(ov, 4),
+                     "overhead_in_csr_spmvs": round(ov / t["csr"], 2)}
     rep = os.path.join(SEL.DATA_DIR, "selector_report.json")
     if os.path.exists(rep):
         r = json.load(open(rep)).get(dname)
@@ -105,12 +110,125 @@ def selector_choices(bases, per, dname):
     return out
 
 
+def _events(torch, stream, fn, steps, warmup, scrub):
+    """Mean event time (ms) of fn over `steps` launches, each after a scrub."""
+    from paper_1805_11938_amd import spmv as S
+    ts = []
+    for r in range(warmup + steps):
+        if scrub:
+            S.scrub(SCRUB)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        if r >= warmup:
+            ts.append((e0, e1))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ts]
+
+
+def bench_batch(args):
+    """512 uneven CSR matrices (rows 10^3..2x10^5, mean row length 4..64,
+    four generators, seed 8) in one persistent launch, against one launch
+    per matrix."""
+    import torch
+    from paper_1805_11938_amd import spmv as S
+    from paper_1805_11938_amd import synth
+    dt = S.F64 if args.dtype == "f64" else S.F32
+    tdt = torch.float64 if dt == S.F64 else torch.float32
+    t0 = time.time()
+    mats, xs, ys, bmin, nnz = [], [], [], 0, 0
+    for i, spec in enumerate(synth.batch_specs(512, seed=8)):
+        A = synth.make(spec)
+        val = A.val.astype(np.float32) if dt == S.F32 else A.val
+        mats.append(S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt))
+        xs.append(torch.from_numpy(synth.vector(A.N, 50 + i)).to("cuda", tdt))
+        ys.append(torch.empty(A.M, dtype=tdt, device="cuda"))
+        bmin += mats[-1].info.bytes_min
+        nnz += A.nnz
+    log(f"[bench] batch of 512: {nnz} nnz, {bmin / 1e9:.2f} GB, built in {time.time() - t0:.1f}s")
+    B = S.Batch(mats)
+    stream = torch.cuda.current_stream()
+    wall = time.perf_counter()
+    tb = _events(torch, stream, lambda: B.run(xs, ys), args.steps, args.warmup, not args.warm)
+    wall = time.perf_counter() - wall
+
+    def each():
+        for m, x, y in zip(mats, xs, ys):
+            m.run(x, y)
+    te = _events(torch, stream, each, args.steps, args.warmup, not args.warm)
+    t, t1 = float(np.mean(tb)), float(np.mean(te))
+    gbps = bmin / (t * 1e-3) / 1e9
+    out = {"metric": "batched SpMV GB/s (one persistent launch over 512 matrices)", "value": round(gbps, 1),
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * wall / (args.steps + args.warmup), 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic (seeded generators)",
+           "config": {"workload": f"512 uneven CSR matrices, {nnz} nnz, seed 8, "
+                                  + ("warm cache" if args.warm else "cold cache")},
+           "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_csr_batched",
+                        "bytes_per_launch": int(bmin), "ms_per_launch": round(t, 5)},
+           "one_launch_per_matrix": {"ms": round(t1, 5), "GBps": round(bmin / (t1 * 1e-3) / 1e9, 1)},
+           "speedup_vs_per_matrix": round(t1 / t, 3)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_spmm(args):
+    """SpMM Y = A X with k = 8 and 16 right-hand sides (row-major, X seed 9)
+    on the 27-point stencil, against k separate SpMVs."""
+    import torch
+    from paper_1805_11938_amd import spmv as S
+    from paper_1805_11938_amd import synth
+    from paper_1805_11938_amd import workloads as W
+    dt = S.F64 if args.dtype == "f64" else S.F32
+    tdt = torch.float64 if dt == S.F64 else torch.float32
+    sv = 8 if dt == S.F64 else 4
+    A = W.make("stencil27_100")
+    val = A.val.astype(np.float32) if dt == S.F32 else A.val
+    Ad = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt)
+    stream = torch.cuda.current_stream()
+    per = {}
+    wall = time.perf_counter()
+    for k in (8, 16):
+        X = torch.from_numpy(synth.uniform(A.N * k, 9, -1.0, 1.0).reshape(A.N, k)).to("cuda", tdt)
+        Y = torch.empty((A.M, k), dtype=tdt, device="cuda")
+        ts = _events(torch, stream, lambda: Ad.spmm(X, Y), args.steps, args.warmup, not args.warm)
+        xcols = [X[:, c].contiguous() for c in range(k)]
+        yv = torch.empty(A.M, dtype=tdt, device="cuda")
+
+        def ksp():
+            for c in range(k):
+                Ad.run(xcols[c], yv)
+        t1 = float(np.mean(_events(torch, stream, ksp, args.steps, args.warmup, not args.warm)))
+        t = float(np.mean(ts))
+        b = A.nnz * (sv + 4) + 4 * (A.M + 1) + A.N * k * sv + A.M * k * sv
+        per[f"k{k}"] = {"ms": round(t, 5), "GBps": round(b / (t * 1e-3) / 1e9, 1), "bytes": int(b),
+                        "GFLOPs": round(2 * A.nnz * k / (t * 1e-3) / 1e9, 1), "k_spmv_ms": round(t1, 5),
+                        "speedup_vs_k_spmv": round(t1 / t, 3)}
+    wall = time.perf_counter() - wall
+    dom = per["k16"]
+    tot_b = sum(v["bytes"] for v in per.values())
+    tot_t = sum(v["ms"] for v in per.values()) * 1e-3
+    out = {"metric": "SpMM GB/s (k = 8, 16 right-hand sides)", "value": round(tot_b / tot_t / 1e9, 1), "unit": "GB/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * wall / (args.steps + args.warmup), 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic (seeded generators)",
+           "config": {"workload": "27-pt stencil 100^3, X row-major N x k, k in {8, 16}, "
+                                  + ("warm cache" if args.warm else "cold cache")},
+           "roofline": {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_csr_spmm k=16",
+                        "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
+           "per_k": per}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batch512", "spmm"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated matrix/format labels to run (default: all)")
@@ -130,6 +248,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "batch512":
+        return bench_batch(args)
+    if args.workload == "spmm":
+        return bench_spmm(args)
     dt = S.F64 if args.dtype == "f64" else S.F32
     tdt = torch.float64 if dt == S.F64 else torch.float32
     sv = 8 if dt == S.F64 else 4

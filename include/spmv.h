@@ -20,10 +20,14 @@
  *   calls that return host data (features, select, to_csr/export to host,
  *   timing) synchronise it.  Library-internal allocations use hipMalloc.
  * - Matrix handles (spmv_mat_t) own their device arrays: creation copies
- *   the caller's arrays, so the caller may free them afterwards.  Handles
- *   are immutable after creation; concurrent runs on different streams
- *   are safe.  x, y, X, Y stay owned by the caller: device pointers of the
- *   handle's dtype.
+ *   the caller's arrays, so the caller may free them afterwards.  Runs of
+ *   distinct handles on different streams are independent.  Three kinds of
+ *   handle keep per-handle device scratch that every run rewrites -- CSR5
+ *   (tile carries), SELL with column slices (partial sums) and CSR built
+ *   with SPMV_FLAG_CSR_WAVES (long-row segment sums) -- so two runs of the
+ *   *same* such handle must not overlap (same stream, or synchronise).
+ *   x, y, X, Y stay owned by the caller: device pointers of the handle's
+ *   dtype.
  * - y is overwritten (beta = 0).  x and y must not overlap.
  */
 #ifndef SPMV_H
@@ -80,7 +84,7 @@ typedef struct {
   int64_t bytes_fmt;     /* bytes one spmv_run streams: format arrays incl. padding/metadata, x once, y once */
   int64_t bytes_min;     /* compulsory CSR bytes nnz*(sv+4) + 4(M+1) + N*sv + M*sv (format independent) */
   int64_t pad_slots;     /* stored slots that hold padding (ELL / SELL / HYB-ELL) */
-  int64_t aux;           /* HYB: COO entries; CSR5: tiles; SELL: chunks; CSR: row blocks */
+  int64_t aux;           /* HYB: COO entries; CSR5: tiles; SELL: chunks; ELL: K; CSR: row blocks */
   spmv_params_t params;  /* the parameters the handle was built with (defaults resolved) */
 } spmv_info_t;
 
@@ -138,7 +142,8 @@ void spmv_mat_free(spmv_mat_t A);
 spmv_status_t spmv_run(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, spmv_stream_t s);
 
 /* Y = A X for k right-hand sides, row-major: X[j*ldx + c], Y[i*ldy + c],
- * c < k <= 64, ldx >= k, ldy >= k.  A must be CSR or SELL. */
+ * c < k <= 64, ldx >= k, ldy >= k.  A must be a CSR handle
+ * (SPMV_ERR_UNSUPPORTED otherwise); columns c >= k of Y are not touched. */
 spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t k, spmv_stream_t s);
 
 /* Batched launch: n CSR handles of one dtype processed by one persistent

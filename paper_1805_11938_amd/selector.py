@@ -302,6 +302,25 @@ def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB):
     return Ad.convert(fmt, **(params or {})), fmt, "exhaustive"
 
 
+PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags"), "csr5": ("csr5_omega", "csr5_sigma"), "ell": (),
+              "sell": ("sell_C", "sell_sigma"), "hyb": ("hyb_K",)}
+
+
+def merge(out_path, parts):
+    """Join collection parts into one table sorted by (matrix, dtype); each
+    format keeps only the parameters that apply to it."""
+    recs = {}
+    for p in parts:
+        for r in load(p):
+            r["params"] = {f: (None if v is None else {k: v[k] for k in PARAM_KEYS[f]})
+                           for f, v in r["params"].items()}
+            recs[(r["index"], r["dtype"])] = r
+    with open(out_path, "w") as fo:
+        for key in sorted(recs):
+            fo.write(json.dumps(recs[key]) + "\n")
+    return len(recs)
+
+
 # ---------------------------------------------------------------- CLI
 
 def main(argv=None):
@@ -316,9 +335,14 @@ def main(argv=None):
     t.add_argument("--dataset", required=True)
     t.add_argument("--out-dir", default=DATA_DIR)
     t.add_argument("--epochs", type=int, default=500)
+    m = sub.add_parser("merge")
+    m.add_argument("out")
+    m.add_argument("parts", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "collect":
         collect(a.start, a.stop, a.out, budget_s=a.budget)
+    elif a.cmd == "merge":
+        log(f"[merge] {merge(a.out, a.parts)} records")
     else:
         recs = load(a.dataset)
         os.makedirs(a.out_dir, exist_ok=True)

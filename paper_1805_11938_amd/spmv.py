@@ -171,12 +171,16 @@ class Matrix:
         self.M, self.N, self.nnz = inf.M, inf.N, inf.nnz
         self._keep = keep
 
-    def __del__(self):
+    def free(self):
         if getattr(self, "h", None):
             lib().spmv_mat_free(self.h)
             self.h = None
 
-    free = __del__
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:  # interpreter shutdown: module globals may already be gone
+            pass
 
     @property
     def params(self) -> dict:
@@ -295,9 +299,12 @@ class Batch:
         check(lib().spmv_batch_run(self.h, xa, ya, stream()))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().spmv_batch_free(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().spmv_batch_free(self.h)
+                self.h = None
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- model
@@ -340,6 +347,9 @@ class Model:
         return FMT_NAMES[best.value], sc
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().spmv_model_free(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().spmv_model_free(self.h)
+                self.h = None
+        except Exception:
+            pass

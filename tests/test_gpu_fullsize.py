@@ -111,3 +111,42 @@ def test_rmat24_sampled_rows(torch, dt):
     with pytest.raises(S.SpmvError) as e:
         Ad.convert("ell")
     assert e.value.status == -4
+
+
+@pytest.mark.timeout(600)
+def test_batch512_sampled_matrices(torch):
+    """The 512-matrix uneven batch in one persistent launch; 24 seeded
+    matrices are compared in full with the oracle, every output checked for
+    being written."""
+    specs = synth.batch_specs(512, seed=8)
+    rng = np.random.default_rng(17)
+    check = set(rng.choice(512, 24, replace=False).tolist()) | {0, 511}
+    mats, xs, ys, refs = [], [], [], {}
+    for i, spec in enumerate(specs):
+        A = synth.make(spec)
+        x64 = synth.vector(A.N, 50 + i)
+        mats.append(S.Matrix.from_host(A))
+        xs.append(device_vec(x64, 0))
+        ys.append(torch.full((A.M,), float("nan"), dtype=torch.float64, device="cuda"))
+        if i in check:
+            refs[i] = reference(A, x64, 0)
+    B = S.Batch(mats)
+    B.run(xs, ys)
+    torch.cuda.synchronize()
+    for i, y in enumerate(ys):
+        yh = y.cpu().numpy()
+        assert not np.isnan(yh).any(), i
+        if i in refs:
+            assert rowwise_err(yh, *refs[i]) <= TOL[0], i
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("k", [8, 16])
+def test_spmm_stencil_full(torch, k):
+    A, _ = workload("stencil27_100")
+    X = synth.uniform(A.N * k, 9, -1.0, 1.0).reshape(A.N, k)
+    Yref = oracle.csr_spmm(A.M, A.ptr, A.col, A.val, X)
+    Y = S.Matrix.from_host(A).spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(k):
+        den = oracle.csr_absspmv(A.M, A.ptr, A.col, A.val, X[:, c].copy())
+        assert rowwise_err(Y[:, c], Yref[:, c], den) <= TOL[0], c
