@@ -6,7 +6,9 @@ Zipf(2) row lengths, mean 16, max 10^4, ~16M nnz), FP64 by default.
 A step is one pass of the hot path over that batch: y = A x once per
 (matrix, format) pair, in the autotuned launch configuration, each launch
 preceded by a cache scrub (512 MB, so neither L2 nor the 256 MB Infinity
-Cache holds the matrix) and bracketed by HIP events on the launch stream.
+Cache holds the matrix) and timed by a pair of HIP events that the launch's
+first kernel records as it starts and its last kernel as it ends
+(spmv_run_timed), so the time is the kernels' own, as rocprofv3 reports it.
 ELL of the Zipf matrix needs 120 GB and is refused by the library's default
 64 GB cap, so a step has 9 launches.
 
@@ -110,22 +112,25 @@ def selector_choices(bases, per, dname):
     return out
 
 
-def _events(torch, stream, fn, steps, warmup, scrub):
-    """Mean event time (ms) of fn over `steps` launches, each after a scrub."""
+def _events(torch, stream, fn, steps, warmup, scrub, kernel_bound=True):
+    """Event times (ms) of fn over `steps` runs, each after a scrub.  With
+    kernel_bound, fn(events) records the pair itself at the start of its first
+    kernel and the end of its last; otherwise markers bracket fn()."""
     from paper_1805_11938_amd import spmv as S
-    ts = []
+    pairs = [S.timing_events() for _ in range(steps)]
+    spare = S.timing_events()
     for r in range(warmup + steps):
+        ev = pairs[r - warmup] if r >= warmup else spare
         if scrub:
             S.scrub(SCRUB)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fn()
-        e1.record(stream)
-        if r >= warmup:
-            ts.append((e0, e1))
+        if kernel_bound:
+            fn(ev)
+        else:
+            ev[0].record(stream)
+            fn()
+            ev[1].record(stream)
     torch.cuda.synchronize()
-    return [a.elapsed_time(b) for a, b in ts]
+    return [a.elapsed_time(b) for a, b in pairs]
 
 
 def bench_batch(args):
@@ -151,13 +156,13 @@ def bench_batch(args):
     B = S.Batch(mats)
     stream = torch.cuda.current_stream()
     wall = time.perf_counter()
-    tb = _events(torch, stream, lambda: B.run(xs, ys), args.steps, args.warmup, not args.warm)
+    tb = _events(torch, stream, lambda ev: B.run(xs, ys, ev), args.steps, args.warmup, not args.warm)
     wall = time.perf_counter() - wall
 
     def each():
         for m, x, y in zip(mats, xs, ys):
             m.run(x, y)
-    te = _events(torch, stream, each, args.steps, args.warmup, not args.warm)
+    te = _events(torch, stream, each, args.steps, args.warmup, not args.warm, kernel_bound=False)
     t, t1 = float(np.mean(tb)), float(np.mean(te))
     gbps = bmin / (t * 1e-3) / 1e9
     out = {"metric": "batched SpMV GB/s (one persistent launch over 512 matrices)", "value": round(gbps, 1),
@@ -193,14 +198,14 @@ def bench_spmm(args):
     for k in (8, 16):
         X = torch.from_numpy(synth.uniform(A.N * k, 9, -1.0, 1.0).reshape(A.N, k)).to("cuda", tdt)
         Y = torch.empty((A.M, k), dtype=tdt, device="cuda")
-        ts = _events(torch, stream, lambda: Ad.spmm(X, Y), args.steps, args.warmup, not args.warm)
+        ts = _events(torch, stream, lambda ev: Ad.spmm_timed(X, Y, ev), args.steps, args.warmup, not args.warm)
         xcols = [X[:, c].contiguous() for c in range(k)]
         yv = torch.empty(A.M, dtype=tdt, device="cuda")
 
         def ksp():
             for c in range(k):
                 Ad.run(xcols[c], yv)
-        t1 = float(np.mean(_events(torch, stream, ksp, args.steps, args.warmup, not args.warm)))
+        t1 = float(np.mean(_events(torch, stream, ksp, args.steps, args.warmup, not args.warm, kernel_bound=False)))
         t = float(np.mean(ts))
         b = A.nnz * (sv + 4) + 4 * (A.M + 1) + A.N * k * sv + A.M * k * sv
         per[f"k{k}"] = {"ms": round(t, 5), "GBps": round(b / (t * 1e-3) / 1e9, 1), "bytes": int(b),
@@ -300,25 +305,28 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] converted {len(launches)} (matrix, format) pairs in {time.time() - t0:.1f}s")
 
-    def step(record):
+    # kernel-bound events: each run records its pair at the start of its first
+    # kernel and the end of its last (see spmv_run_timed)
+    spare = S.timing_events()
+    for L in launches:
+        L["pairs"] = [S.timing_events() for _ in range(args.steps)]
+
+    def step(i):
         for L in launches:
             if not args.warm:
                 S.scrub(SCRUB)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            L["m"].run(L["x"], L["y"])
-            e1.record(stream)
-            if record:
-                L.setdefault("ev", []).append((e0, e1))
+            ev = L["pairs"][i] if i >= 0 else spare
+            L["m"].run_timed(L["x"], L["y"], ev)
+            if i >= 0:
+                L.setdefault("ev", []).append(ev)
 
     for _ in range(args.warmup):
-        step(False)
+        step(-1)
     torch.cuda.synchronize()
     log(f"[bench] warmup done; timing {args.steps} steps")
     t_wall = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
+    for i in range(args.steps):
+        step(i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
 

@@ -155,6 +155,22 @@ void spmv_batch_free(spmv_batch_t b);
 
 /* ---------------------------------------------------------- measurement */
 
+/* Timed variants of spmv_run, spmv_spmm and spmv_batch_run (the byte and
+ * time model of the measurements, Sec. IV-B).  start_event / stop_event are
+ * hipEvent_t created by the caller (with timing enabled).  The call's first
+ * kernel records start_event as it begins and its last kernel records
+ * stop_event as it ends (the kernels are launched with hipExtLaunchKernel),
+ * so hipEventElapsedTime(start, stop) is the run's kernel time without the
+ * dispatch latency of separate event records.  A call that launches no
+ * kernel (M = 0) records both events on s.  Errors as the untimed calls;
+ * SPMV_ERR_INVALID_ARG for a null event. */
+spmv_status_t spmv_run_timed(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, spmv_stream_t s,
+                             void* start_event, void* stop_event);
+spmv_status_t spmv_spmm_timed(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t k,
+                              spmv_stream_t s, void* start_event, void* stop_event);
+spmv_status_t spmv_batch_run_timed(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s,
+                                   void* start_event, void* stop_event);
+
 /* Timing in the manner of Sec. V-B: repeat until the 95% confidence
  * interval of the mean is narrower than rel_ci (0.05 = the paper's 5%
  * gap), with at least min_reps and at most max_reps launches, after

@@ -292,4 +292,11 @@ spmv_status_t spmv_run(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, spm
   return dispatch_run(A, x, y, hs(s));
 }
 
+spmv_status_t spmv_run_timed(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, spmv_stream_t s,
+                             void* start_event, void* stop_event) {
+  if (!start_event || !stop_event) return fail(SPMV_ERR_INVALID_ARG, "null event");
+  return timed_call((hipEvent_t)start_event, (hipEvent_t)stop_event, hs(s),
+                    [&] { return spmv_run(fmt, A, x, y, s); });
+}
+
 }  // extern "C"

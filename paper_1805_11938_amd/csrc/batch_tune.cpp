@@ -31,6 +31,13 @@ spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64
   return run_spmm(A, X, ldx, Y, ldy, k, hs(s));
 }
 
+spmv_status_t spmv_spmm_timed(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t k,
+                              spmv_stream_t s, void* start_event, void* stop_event) {
+  if (!start_event || !stop_event) return fail(SPMV_ERR_INVALID_ARG, "null event");
+  return timed_call((hipEvent_t)start_event, (hipEvent_t)stop_event, hs(s),
+                    [&] { return spmv_spmm(A, X, ldx, Y, ldy, k, s); });
+}
+
 spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* out) {
   if (!A || n <= 0 || !out) return fail(SPMV_ERR_INVALID_ARG, "batch arguments");
   *out = nullptr;
@@ -80,6 +87,13 @@ spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* 
   }
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(b->nitems, 1), resident_blocks(6));
   return launch_batched(b->dt, b->n, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st);
+}
+
+spmv_status_t spmv_batch_run_timed(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s,
+                                   void* start_event, void* stop_event) {
+  if (!start_event || !stop_event) return fail(SPMV_ERR_INVALID_ARG, "null event");
+  return timed_call((hipEvent_t)start_event, (hipEvent_t)stop_event, hs(s),
+                    [&] { return spmv_batch_run(b, x, y, s); });
 }
 
 void spmv_batch_free(spmv_batch_t b) {

@@ -1,6 +1,7 @@
 // Internal declarations of libspmv (gfx950).  Not part of the C-ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,6 +64,51 @@ int64_t default_max_bytes();
 // Workgroups that fit on the device at once when each CU holds per_cu of them
 // (persistent kernels size their grid with it).
 int64_t resident_blocks(int per_cu);
+
+// Kernel-bound timing.  While a RunTiming is armed on the calling thread,
+// every kernel of a run path is launched through hipExtLaunchKernel: the
+// first records `start` as it begins and each records `stop` as it ends
+// (the last one's value stays), so stop - start spans exactly the kernels
+// of one run, without the dispatch latency that separate event markers add.
+struct RunTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local RunTiming* g_timing;
+
+struct TimingArm {
+  RunTiming t;
+  RunTiming* prev;
+  TimingArm(hipEvent_t a, hipEvent_t b) : prev(g_timing) {
+    t.start = a;
+    t.stop = b;
+    g_timing = &t;
+  }
+  ~TimingArm() { g_timing = prev; }
+};
+
+// Runs f() with kernel-bound timing armed; a call that launched no kernel
+// (an empty matrix) records both events on the stream.
+template <typename F>
+inline spmv_status_t timed_call(hipEvent_t a, hipEvent_t b, hipStream_t s, F&& f) {
+  TimingArm arm(a, b);
+  const spmv_status_t st = f();
+  if (st == SPMV_OK && arm.t.start) {
+    SPMV_HIP(hipEventRecord(a, s));
+    SPMV_HIP(hipEventRecord(b, s));
+  }
+  return st;
+}
+
+template <typename... KArgs, typename... Args>
+inline void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (g_timing) {
+    hipEvent_t a = g_timing->start;
+    g_timing->start = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, g_timing->stop, 0, static_cast<KArgs>(args)...);
+  } else {
+    kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
+  }
+}
 
 }  // namespace spmv
 

@@ -387,27 +387,27 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   const T* val = (const T*)A->val;
   if (V == 0) {
     if (!(A->params.flags & SPMV_FLAG_CSR_WAVES))
-      k_csr_rows<T, true><<<(unsigned)A->nblk, BS, 0, s>>>(A->nblk, A->blk_row, ptr, A->col, val, x, y);
+      launch(k_csr_rows<T, true>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y);
     else
     {
       const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nunits + A->nseg, BS / WAVE), resident_blocks(8));
-      k_csr_waves<T><<<g, BS, 0, s>>>(
+      launch(k_csr_waves<T>, g, BS, s, 
           A->nunits, A->unit_row, A->nseg, A->segs, A->seg_part, ptr, A->col, val, x, y);
       if (A->nlong > 0) {
         SPMV_LAUNCH_CHECK();
-        k_csr_long_fix<T><<<(unsigned)cdiv(A->nlong, BS / WAVE), BS, 0, s>>>(A->nlong, A->longs, A->seg_part, y);
+        launch(k_csr_long_fix<T>, (unsigned)cdiv(A->nlong, BS / WAVE), BS, s, A->nlong, A->longs, A->seg_part, y);
       }
     }
   } else {
     const unsigned g = (unsigned)cdiv(A->M, BS / V);
     switch (V) {
-      case 1: k_csr_vector<T, 1><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
-      case 2: k_csr_vector<T, 2><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
-      case 4: k_csr_vector<T, 4><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
-      case 8: k_csr_vector<T, 8><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
-      case 16: k_csr_vector<T, 16><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
-      case 32: k_csr_vector<T, 32><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
-      case 64: k_csr_vector<T, 64><<<g, BS, 0, s>>>(A->M, ptr, A->col, val, x, y); break;
+      case 1: launch(k_csr_vector<T, 1>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 2: launch(k_csr_vector<T, 2>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 4: launch(k_csr_vector<T, 4>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 8: launch(k_csr_vector<T, 8>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 16: launch(k_csr_vector<T, 16>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 32: launch(k_csr_vector<T, 32>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 64: launch(k_csr_vector<T, 64>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
       default: return fail(SPMV_ERR_UNSUPPORTED, "csr_lanes_per_row must be 0 or a power of two <= 64 (got %d)", V);
     }
   }
@@ -489,10 +489,10 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
   if (A->M == 0) return SPMV_OK;
   const unsigned g = (unsigned)std::min<int64_t>(A->nblk, resident_blocks(4));
   if (A->dt == SPMV_F64)
-    k_csr_spmm<double><<<g, BS, 0, s>>>(A->nblk, A->blk_row, A->ptr, A->col, (const double*)A->val,
+    launch(k_csr_spmm<double>, g, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const double*)A->val,
                                         (const double*)X, ldx, (double*)Y, ldy, k);
   else
-    k_csr_spmm<float><<<g, BS, 0, s>>>(A->nblk, A->blk_row, A->ptr, A->col, (const float*)A->val, (const float*)X,
+    launch(k_csr_spmm<float>, g, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const float*)A->val, (const float*)X,
                                        ldx, (float*)Y, ldy, k);
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
@@ -533,9 +533,9 @@ spmv_status_t launch_batched(int dt, int32_t n, int64_t nitems, const void* desc
                              void* const* ys, int grid, hipStream_t s) {
   if (nitems <= 0) return SPMV_OK;
   if (dt == SPMV_F64)
-    k_csr_batched<double><<<grid, BS, 0, s>>>(n, nitems, (const BatchDesc*)desc, xs, ys);
+    launch(k_csr_batched<double>, grid, BS, s, n, nitems, (const BatchDesc*)desc, xs, ys);
   else
-    k_csr_batched<float><<<grid, BS, 0, s>>>(n, nitems, (const BatchDesc*)desc, xs, ys);
+    launch(k_csr_batched<float>, grid, BS, s, n, nitems, (const BatchDesc*)desc, xs, ys);
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
 }

@@ -448,11 +448,11 @@ __global__ __launch_bounds__(BS) void k_csr5_fix(int64_t nchains, const int32_t*
 template <typename T, bool EMPTY, bool W64>
 static void launch_c5w(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
   switch (a.sigma) {
-    case 4: k_csr5<T, 4, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    case 8: k_csr5<T, 8, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    case 16: k_csr5<T, 16, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    case 32: k_csr5<T, 32, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
-    default: k_csr5<T, 0, EMPTY, W64><<<grid, BS, 0, s>>>(a, val, x, y); break;
+    case 4: launch(k_csr5<T, 4, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
+    case 8: launch(k_csr5<T, 8, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
+    case 16: launch(k_csr5<T, 16, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
+    case 32: launch(k_csr5<T, 32, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
+    default: launch(k_csr5<T, 0, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
   }
 }
 
@@ -488,7 +488,7 @@ static spmv_status_t run_csr5_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) 
   else launch_c5<T, false>(a, grid, (const T*)A->val, x, y, s);
   SPMV_LAUNCH_CHECK();
   if (A->nchains > 0) {
-    k_csr5_fix<T><<<(unsigned)cdiv(A->nchains, BS / WAVE), BS, 0, s>>>(A->nchains, A->chains, A->carry, y);
+    launch(k_csr5_fix<T>, (unsigned)cdiv(A->nchains, BS / WAVE), BS, s, A->nchains, A->chains, A->carry, y);
     SPMV_LAUNCH_CHECK();
   }
   return SPMV_OK;

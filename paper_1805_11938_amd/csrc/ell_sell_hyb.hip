@@ -170,12 +170,12 @@ static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const
   if (M == 0) return SPMV_OK;
   if ((M & 1) == 0 && ((uintptr_t)y & (2 * sizeof(T) - 1)) == 0) {
     const unsigned g2 = (unsigned)std::min<int64_t>(cdiv(M / 2, BS), resident_blocks(8));
-    k_ell2<T><<<g2, BS, 0, s>>>(M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
+    launch(k_ell2<T>, g2, BS, s, M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
     SPMV_LAUNCH_CHECK();
     return SPMV_OK;
   }
   const unsigned g = (unsigned)std::min<int64_t>(cdiv(M, BS), resident_blocks(8));  // persistent grid
-  k_ell<T><<<g, BS, 0, s>>>(M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
+  launch(k_ell<T>, g, BS, s, M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
 }
@@ -378,17 +378,17 @@ template <typename T, int LOGC>
 static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nitems << LOGC, BS), resident_blocks(8));
   if (A->perm)
-    k_sell<T, LOGC, true><<<g, BS, 0, s>>>(A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
+    launch(k_sell<T, LOGC, true>, g, BS, s, A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
                                            (const T*)x, (T*)y, A->part);
   else
-    k_sell<T, LOGC, false><<<g, BS, 0, s>>>(A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
+    launch(k_sell<T, LOGC, false>, g, BS, s, A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
                                             (const T*)x, (T*)y, A->part);
   if (A->nwide > 0) {
     const unsigned gf = (unsigned)cdiv(A->nwide << LOGC, BS);
     if (A->perm)
-      k_sell_fix<T, true><<<gf, BS, 0, s>>>(A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
+      launch(k_sell_fix<T, true>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
     else
-      k_sell_fix<T, false><<<gf, BS, 0, s>>>(A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
+      launch(k_sell_fix<T, false>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
   }
 }
 
@@ -670,7 +670,7 @@ static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_
   if (A->M == 0) return SPMV_OK;
   SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, s));
   if (A->ncoo > 0) {
-    k_coo<T><<<(unsigned)A->ncoo_blk, BS, 0, s>>>(A->coo_blk, A->crow, A->ccol, (const T*)A->cval, (const T*)x, (T*)y);
+    launch(k_coo<T>, (unsigned)A->ncoo_blk, BS, s, A->coo_blk, A->crow, A->ccol, (const T*)A->cval, (const T*)x, (T*)y);
     SPMV_LAUNCH_CHECK();
   }
   return SPMV_OK;

@@ -10,6 +10,7 @@ namespace spmv {
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
+thread_local RunTiming* g_timing = nullptr;
 
 void set_error(const char* fmt, ...) {
   char buf[1024];

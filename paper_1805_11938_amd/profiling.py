@@ -68,7 +68,7 @@ def _segments(disp):
             if cur:
                 segs.append(cur)
             cur = []
-        elif cur is not None and k.split("<")[0] in RUN_KERNELS:
+        elif cur is not None and k.split("<")[0].split("::")[-1] in RUN_KERNELS:
             cur.append((k, v))
     if cur:
         segs.append(cur)

@@ -60,7 +60,8 @@ EXPORTED = [
     "spmv_batch_create", "spmv_batch_run", "spmv_batch_free", "spmv_time", "spmv_scrub", "spmv_copy_probe",
     "spmv_autotune", "spmv_features", "spmv_model_create", "spmv_model_load", "spmv_model_save",
     "spmv_model_params", "spmv_model_free", "spmv_select", "spmv_mlp_forward", "spmv_mlp_backward", "spmv_mlp_adam",
-    "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train",
+    "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train", "spmv_run_timed", "spmv_spmm_timed",
+    "spmv_batch_run_timed",
 ]
 
 _L = None
@@ -108,6 +109,9 @@ def lib():
             "spmv_scale_features": (st, [vp, i32, vp, vp, vp, vp]),
             "spmv_feature_range": (st, [vp, i32, vp, vp, vp]),
             "spmv_mlp_train": (st, [vp, vp, vp, i32, vp, i32, i32, ctypes.c_float, vp, vp]),
+            "spmv_run_timed": (st, [st, vp, vp, vp, vp, vp, vp]),
+            "spmv_spmm_timed": (st, [vp, vp, i64, vp, i64, i32, vp, vp, vp]),
+            "spmv_batch_run_timed": (st, [vp, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -134,6 +138,21 @@ def _torch():
 def stream():
     """The current torch (HIP) stream as a void*."""
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def timing_events():
+    """A (start, stop) pair of timing-enabled torch events, created on the
+    device (recorded once) so their handles can be passed to the timed runs."""
+    torch = _torch()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    b.record()
+    return a, b
+
+
+def _ev(e):
+    return ctypes.c_void_p(e.cuda_event)
 
 
 def dptr(t):
@@ -247,6 +266,18 @@ class Matrix:
         check(lib().spmv_run(FMT[self.fmt], self.h, dptr(x), dptr(y), stream()))
         return y
 
+    def run_timed(self, x, y, events):
+        """As run; events = (start, stop) from timing_events() are recorded at
+        the start of the run's first kernel and the end of its last."""
+        check(lib().spmv_run_timed(FMT[self.fmt], self.h, dptr(x), dptr(y), stream(), _ev(events[0]),
+                                   _ev(events[1])))
+        return y
+
+    def spmm_timed(self, X, Y, events):
+        check(lib().spmv_spmm_timed(self.h, dptr(X), X.stride(0), dptr(Y), Y.stride(0), X.shape[1], stream(),
+                                    _ev(events[0]), _ev(events[1])))
+        return Y
+
     def spmm(self, X, Y=None):
         torch = _torch()
         k = X.shape[1]
@@ -293,10 +324,13 @@ class Batch:
         self.h = ctypes.c_void_p()
         check(lib().spmv_batch_create(arr, len(self.mats), ctypes.byref(self.h)))
 
-    def run(self, xs, ys):
+    def run(self, xs, ys, events=None):
         xa = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
         ya = (ctypes.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
-        check(lib().spmv_batch_run(self.h, xa, ya, stream()))
+        if events is None:
+            check(lib().spmv_batch_run(self.h, xa, ya, stream()))
+        else:
+            check(lib().spmv_batch_run_timed(self.h, xa, ya, stream(), _ev(events[0]), _ev(events[1])))
 
     def __del__(self):
         try:
