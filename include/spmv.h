@@ -77,6 +77,10 @@ typedef struct {
 
 #define SPMV_FLAG_NO_CHECK 1u /* skip the column checks of spmv_mat_from_csr (ptr is always checked) */
 #define SPMV_FLAG_CSR_WAVES 2u /* CSR: per-wave row units (+ long-row segments) instead of workgroup row blocks */
+#define SPMV_FLAG_LINEAR 4u    /* CSR row blocks, ELL and HYB's ELL part: workgroups take rows in launch order
+                                  instead of each XCD taking a contiguous range of rows */
+#define SPMV_FLAG_SELL_SLICES 8u /* SELL: always the persistent column-slice kernel (default: chunks at most
+                                    32 wide use the one-pass narrow kernel) */
 
 typedef struct {
   int32_t fmt, dtype;

@@ -5,10 +5,10 @@
 #include "common.h"
 
 namespace spmv {
-spmv_status_t launch_batched(int dt, int32_t n, int64_t nitems, const void* desc, const void* const* xs,
+spmv_status_t launch_batched(int dt, int64_t nitems, const void* items, const void* const* xs,
                              void* const* ys, int grid, hipStream_t s);
-size_t batch_desc_size();
-void batch_desc_fill(void* dst, const spmv_mat_s* A, int64_t item0);
+size_t batch_item_size();
+spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s);
 spmv_status_t time_run(spmv_mat_s* A, const void* x, void* y, int warmup, int min_reps, int max_reps, double rel_ci,
                        int64_t scrub_bytes, hipStream_t s, double out[5]);
 }  // namespace spmv
@@ -19,7 +19,7 @@ struct spmv_batch_s {
   int32_t n = 0;
   spmv_dtype_t dt = SPMV_F64;
   int64_t nitems = 0;
-  void* desc = nullptr;   // device: n descriptors
+  void* desc = nullptr;   // device: one record per work item (matrix, row and nonzero range)
   void** xy = nullptr;    // device: n x pointers then n y pointers
   std::vector<const void*> last;  // host copy of the pointers last uploaded
 };
@@ -49,18 +49,18 @@ spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* ou
   if (!b) return fail(SPMV_ERR_OOM, "host allocation failed");
   b->n = n;
   b->dt = A[0]->dt;
-  const size_t ds = batch_desc_size();
-  std::vector<char> host(ds * n);
   int64_t items = 0;
-  for (int32_t i = 0; i < n; ++i) {  // work items: every row block of every matrix, in order
-    batch_desc_fill(host.data() + ds * i, A[i], items);
-    items += A[i]->nblk;
-  }
+  for (int32_t i = 0; i < n; ++i) items += A[i]->nblk;  // every row block of every matrix, in order
   b->nitems = items;
-  spmv_status_t st = dmalloc(&b->desc, ds * n);
+  const size_t is = batch_item_size();
+  spmv_status_t st = dmalloc(&b->desc, is * (size_t)std::max<int64_t>(items, 1));
   if (st == SPMV_OK) st = dmalloc((void**)&b->xy, sizeof(void*) * 2 * n);
-  if (st == SPMV_OK && hipMemcpy(b->desc, host.data(), ds * n, hipMemcpyHostToDevice) != hipSuccess)
-    st = fail(SPMV_ERR_HIP, "batch descriptor upload failed");
+  int64_t at = 0;
+  for (int32_t i = 0; i < n && st == SPMV_OK; ++i) {
+    st = batch_items_fill(A[i], i, (char*)b->desc + is * at, nullptr);
+    at += A[i]->nblk;
+  }
+  if (st == SPMV_OK && hipDeviceSynchronize() != hipSuccess) st = fail(SPMV_ERR_HIP, "batch item table build failed");
   if (st != SPMV_OK) {
     dfree(b->desc);
     dfree(b->xy);
@@ -86,7 +86,7 @@ spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* 
     b->last = ptrs;
   }
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(b->nitems, 1), resident_blocks(6));
-  return launch_batched(b->dt, b->n, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st);
+  return launch_batched(b->dt, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st);
 }
 
 spmv_status_t spmv_batch_run_timed(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s,
@@ -123,8 +123,9 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
   };
   switch (fmt) {
     case SPMV_FMT_CSR:
-      add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags &= ~SPMV_FLAG_CSR_WAVES; });
+      add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags &= ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR); });
       add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags |= SPMV_FLAG_CSR_WAVES; });
+      add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags = (p.flags & ~SPMV_FLAG_CSR_WAVES) | SPMV_FLAG_LINEAR; });
       for (int V : {4, 8, 16, 32}) add([V](spmv_params_t& p) { p.csr_lanes_per_row = V; });
       break;
     case SPMV_FMT_CSR5:

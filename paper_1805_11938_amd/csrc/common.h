@@ -146,6 +146,7 @@ struct spmv_mat_s {
   int32_t* scol = nullptr;
   void* sval = nullptr;
   int64_t nitems = 0, nwide = 0;  // column-slice work items; chunks split into several slices
+  int32_t sell_maxw = 0;          // widest chunk (= longest row)
   int2* items = nullptr;          // (chunk, first column) per item
   int4* wide = nullptr;           // (chunk, first item, item count) per split chunk
   double* part = nullptr;         // nitems * C partial sums (run scratch, split chunks only)

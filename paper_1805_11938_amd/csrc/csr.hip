@@ -167,13 +167,13 @@ constexpr int CSR_RCAP = 512;  // row pointers a block stages in LDS
 
 // One row block (all threads of the workgroup call this with the same rows).
 template <typename T>
-__device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, const int32_t* __restrict__ ptr,
+__device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, int64_t k0, int64_t k1,
+                                               const int32_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col, const T* __restrict__ val,
                                                const T* __restrict__ x, T* __restrict__ y, double* prod,
                                                int32_t* sptr) {
   if (r0 >= r1) return;
   const int t = threadIdx.x;
-  const int64_t k0 = ptr[r0], k1 = ptr[r1];
   const int64_t E = k1 - k0, nr = r1 - r0;
   if (E <= CSR_CAP) {
     const bool staged = nr <= CSR_RCAP;
@@ -239,7 +239,8 @@ __global__ __launch_bounds__(BS) void k_csr_rows(int64_t nblk, const int32_t* __
   __shared__ int32_t sptr[CSR_RCAP + 1];
   const uint32_t b = XCD ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   if (b >= nblk) return;
-  csr_rows_block<T>(blk_row[b], blk_row[b + 1], ptr, col, val, x, y, prod, sptr);
+  const int64_t r0 = blk_row[b], r1 = blk_row[b + 1];
+  csr_rows_block<T>(r0, r1, ptr[r0], ptr[r1], ptr, col, val, x, y, prod, sptr);
 }
 
 // ------------------------------------------------------------ wave units
@@ -386,9 +387,12 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   const int32_t* ptr = A->ptr;
   const T* val = (const T*)A->val;
   if (V == 0) {
-    if (!(A->params.flags & SPMV_FLAG_CSR_WAVES))
-      launch(k_csr_rows<T, true>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y);
-    else
+    if (!(A->params.flags & SPMV_FLAG_CSR_WAVES)) {
+      if (A->params.flags & SPMV_FLAG_LINEAR)
+        launch(k_csr_rows<T, false>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y);
+      else
+        launch(k_csr_rows<T, true>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y);
+    } else
     {
       const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nunits + A->nseg, BS / WAVE), resident_blocks(8));
       launch(k_csr_waves<T>, g, BS, s, 
@@ -444,22 +448,48 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
     if (r0 >= r1) continue;
     const int64_t k0 = ptr[r0], E = ptr[r1] - k0;
     if (E <= SPMM_CAP) {
-      for (int64_t q = t; q < E; q += BS) {
-        scol[q] = ldnt(col + k0 + q);
-        sval[q] = ldnt(val + k0 + q);
+      if (E > 0) {  // all staging loads in flight (clamped, branch-free), then the LDS stores
+        int32_t cs[SPMM_CAP / BS];
+        T vs[SPMM_CAP / BS];
+        const uint32_t Em1 = (uint32_t)E - 1;
+#pragma unroll
+        for (int j = 0; j < SPMM_CAP / BS; ++j) {
+          const uint32_t q = (uint32_t)(t + j * BS), qq = q < (uint32_t)E ? q : Em1;
+          cs[j] = ldnt32(col + k0, qq);
+          vs[j] = ldnt32(val + k0, qq);
+        }
+#pragma unroll
+        for (int j = 0; j < SPMM_CAP / BS; ++j) {
+          const int q = t + j * BS;
+          if (q < E) {
+            scol[q] = cs[j];
+            sval[q] = vs[j];
+          }
+        }
       }
       __syncthreads();
       if (g < G)
         for (int64_t r = r0 + g; r < r1; r += G) {
           const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
-          double s0 = 0.0, s1 = 0.0;
-          int q = a;
-          for (; q + 1 < e; q += 2) {
-            s0 += (double)sval[q] * (double)X[(int64_t)scol[q] * ldx + c];
-            s1 += (double)sval[q + 1] * (double)X[(int64_t)scol[q + 1] * ldx + c];
+          double s4[4] = {0.0, 0.0, 0.0, 0.0};
+          // 8 nonzeros at a time, all 8 gathers of X rows in flight; the
+          // last group repeats entry e-1 for its unused places and masks them
+          for (int q = a; q < e; q += 8) {
+            const int n = e - q < 8 ? e - q : 8;
+            int32_t cq[8];
+            T vq[8], xq[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int qq = q + (u < n ? u : n - 1);
+              cq[u] = scol[qq];
+              vq[u] = sval[qq];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xq[u] = X[(int64_t)cq[u] * ldx + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s4[u & 3] += u < n ? (double)vq[u] * (double)xq[u] : 0.0;
           }
-          if (q < e) s0 += (double)sval[q] * (double)X[(int64_t)scol[q] * ldx + c];
-          Y[r * ldy + c] = (T)(s0 + s1);
+          Y[r * ldy + c] = (T)((s4[0] + s4[1]) + (s4[2] + s4[3]));
         }
       __syncthreads();
     } else {
@@ -500,54 +530,68 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
 
 // ------------------------------------------------------- batched launch
 // A work item is one row block of one matrix; items are numbered across
-// the batch (prefix of row-block counts), so the list is balanced by
-// rows-plus-nonzeros.  A fixed grid strides over the item list.
-struct BatchDesc {
+// the batch in matrix order, so the list is balanced by rows-plus-nonzeros.
+// The item table, built once when the batch is created, holds each item's
+// matrix arrays, row range and nonzero range, so a workgroup issues its
+// column and value loads right after reading one record (no search over
+// the matrices, no dependent row-pointer loads).  A fixed grid strides over
+// the table.
+struct BatchItem {
   const int32_t* ptr;
   const int32_t* col;
   const void* val;
-  const int32_t* blk_row;
-  int64_t item0;  // first global item of this matrix
+  int32_t m, r0, r1, k0, k1, pad;
 };
 
-template <typename T>
-__global__ __launch_bounds__(BS) void k_csr_batched(int32_t n, int64_t nitems, const BatchDesc* __restrict__ desc,
-                                                    const void* const* __restrict__ xs, void* const* __restrict__ ys) {
-  __shared__ double prod[CSR_CAP];
-  __shared__ int32_t sptr[CSR_RCAP + 1];
-  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    int lo = 0, hi = n - 1;  // last matrix with item0 <= it
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (desc[mid].item0 <= it) lo = mid;
-      else hi = mid - 1;
-    }
-    const BatchDesc d = desc[lo];
-    const int64_t b = it - d.item0;
-    csr_rows_block<T>(d.blk_row[b], d.blk_row[b + 1], d.ptr, d.col, (const T*)d.val, (const T*)xs[lo], (T*)ys[lo],
-                      prod, sptr);
+__global__ void k_batch_items(int64_t nblk, const int32_t* __restrict__ blk_row, const int32_t* __restrict__ ptr,
+                              const int32_t* col, const void* val, int32_t m, BatchItem* __restrict__ out) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r0 = blk_row[b], r1 = blk_row[b + 1];
+    BatchItem it;
+    it.ptr = ptr;
+    it.col = col;
+    it.val = val;
+    it.m = m;
+    it.r0 = r0;
+    it.r1 = r1;
+    it.k0 = ptr[r0];
+    it.k1 = ptr[r1];
+    it.pad = 0;
+    out[b] = it;
   }
 }
 
-spmv_status_t launch_batched(int dt, int32_t n, int64_t nitems, const void* desc, const void* const* xs,
-                             void* const* ys, int grid, hipStream_t s) {
-  if (nitems <= 0) return SPMV_OK;
-  if (dt == SPMV_F64)
-    launch(k_csr_batched<double>, grid, BS, s, n, nitems, (const BatchDesc*)desc, xs, ys);
-  else
-    launch(k_csr_batched<float>, grid, BS, s, n, nitems, (const BatchDesc*)desc, xs, ys);
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_batched(int64_t nitems, const BatchItem* __restrict__ items,
+                                                    const void* const* __restrict__ xs, void* const* __restrict__ ys) {
+  __shared__ double prod[CSR_CAP];
+  __shared__ int32_t sptr[CSR_RCAP + 1];
+  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const BatchItem it = items[i];
+    csr_rows_block<T>(it.r0, it.r1, it.k0, it.k1, it.ptr, it.col, (const T*)it.val, (const T*)xs[it.m],
+                      (T*)ys[it.m], prod, sptr);
+  }
+}
+
+spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s) {
+  if (A->nblk <= 0) return SPMV_OK;
+  k_batch_items<<<(unsigned)std::min<int64_t>(cdiv(A->nblk, BS), 1024), BS, 0, s>>>(
+      A->nblk, A->blk_row, A->ptr, A->col, A->val, m, (BatchItem*)items);
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
 }
 
-size_t batch_desc_size() { return sizeof(BatchDesc); }
-void batch_desc_fill(void* dst, const spmv_mat_s* A, int64_t item0) {
-  BatchDesc* d = (BatchDesc*)dst;
-  d->ptr = A->ptr;
-  d->col = A->col;
-  d->val = A->val;
-  d->blk_row = A->blk_row;
-  d->item0 = item0;
+size_t batch_item_size() { return sizeof(BatchItem); }
+
+spmv_status_t launch_batched(int dt, int64_t nitems, const void* items, const void* const* xs, void* const* ys,
+                             int grid, hipStream_t s) {
+  if (nitems <= 0) return SPMV_OK;
+  if (dt == SPMV_F64)
+    launch(k_csr_batched<double>, grid, BS, s, nitems, (const BatchItem*)items, xs, ys);
+  else
+    launch(k_csr_batched<float>, grid, BS, s, nitems, (const BatchItem*)items, xs, ys);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
 }
 
 // ------------------------------------------------------------ creation

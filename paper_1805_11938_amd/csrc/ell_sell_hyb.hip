@@ -164,10 +164,87 @@ __global__ __launch_bounds__(BS) void k_ell2(int64_t M, int64_t K, const int32_t
   }
 }
 
+// Narrow ELL (K <= 32): one row per lane with every slot's column and value
+// load in flight at once, then every gather, then the sum -- two memory
+// round trips per row in total.  The kernel is instantiated for each K, so
+// no slot is loaded twice or masked.  With XCD, blocks are remapped so that
+// each XCD takes a contiguous range of rows (the x window of neighbouring
+// rows stays in one L2).
+template <typename T, int KC, bool XCD>
+__global__ __launch_bounds__(BS) void k_ell_kc(int64_t M, const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                               const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = (int64_t)(XCD ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * BS + threadIdx.x;
+  if (i >= M) return;
+  int32_t c[KC];
+  T v[KC], xv[KC];
+#pragma unroll
+  for (int u = 0; u < KC; ++u) c[u] = ldnt32(ecol + (int64_t)u * M, (uint32_t)i);
+#pragma unroll
+  for (int u = 0; u < KC; ++u) v[u] = ldnt32(eval + (int64_t)u * M, (uint32_t)i);
+  issue_fence();
+#pragma unroll
+  for (int u = 0; u < KC; ++u) xv[u] = ld32(x, (uint32_t)(c[u] >= 0 ? c[u] : 0));
+  issue_fence();
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < KC; ++u) s[u & 3] += c[u] >= 0 ? (double)v[u] * (double)xv[u] : 0.0;
+  y[i] = (T)((s[0] + s[1]) + (s[2] + s[3]));
+}
+
+template <typename T, bool XCD>
+static void launch_ell_kc(int64_t M, int32_t k, const int32_t* ecol, const void* eval, const void* x, void* y,
+                          unsigned g, hipStream_t s) {
+  switch (k) {
+    case 1: launch(k_ell_kc<T, 1, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 2: launch(k_ell_kc<T, 2, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 3: launch(k_ell_kc<T, 3, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 4: launch(k_ell_kc<T, 4, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 5: launch(k_ell_kc<T, 5, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 6: launch(k_ell_kc<T, 6, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 7: launch(k_ell_kc<T, 7, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 8: launch(k_ell_kc<T, 8, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 9: launch(k_ell_kc<T, 9, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 10: launch(k_ell_kc<T, 10, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 11: launch(k_ell_kc<T, 11, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 12: launch(k_ell_kc<T, 12, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 13: launch(k_ell_kc<T, 13, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 14: launch(k_ell_kc<T, 14, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 15: launch(k_ell_kc<T, 15, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 16: launch(k_ell_kc<T, 16, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 17: launch(k_ell_kc<T, 17, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 18: launch(k_ell_kc<T, 18, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 19: launch(k_ell_kc<T, 19, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 20: launch(k_ell_kc<T, 20, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 21: launch(k_ell_kc<T, 21, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 22: launch(k_ell_kc<T, 22, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 23: launch(k_ell_kc<T, 23, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 24: launch(k_ell_kc<T, 24, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 25: launch(k_ell_kc<T, 25, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 26: launch(k_ell_kc<T, 26, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 27: launch(k_ell_kc<T, 27, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 28: launch(k_ell_kc<T, 28, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 29: launch(k_ell_kc<T, 29, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 30: launch(k_ell_kc<T, 30, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 31: launch(k_ell_kc<T, 31, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 32: launch(k_ell_kc<T, 32, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    default: break;
+  }
+}
+
 template <typename T>
 static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const void* eval, const void* x, void* y,
-                                hipStream_t s) {
+                                bool xcd, hipStream_t s) {
   if (M == 0) return SPMV_OK;
+  if (K >= 1 && K <= 32) {
+    const unsigned g = (unsigned)cdiv(M, BS);
+    const int32_t k = (int32_t)K;
+    if (xcd)
+      launch_ell_kc<T, true>(M, k, ecol, eval, x, y, g, s);
+    else
+      launch_ell_kc<T, false>(M, k, ecol, eval, x, y, g, s);
+    SPMV_LAUNCH_CHECK();
+    return SPMV_OK;
+  }
   if ((M & 1) == 0 && ((uintptr_t)y & (2 * sizeof(T) - 1)) == 0) {
     const unsigned g2 = (unsigned)std::min<int64_t>(cdiv(M / 2, BS), resident_blocks(8));
     launch(k_ell2<T>, g2, BS, s, M, K, ecol, (const T*)eval, (const T*)x, (T*)y);
@@ -181,8 +258,9 @@ static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const
 }
 
 spmv_status_t run_ell(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  if (A->dt == SPMV_F64) return launch_ell<double>(A->M, A->K, A->ecol, A->eval, x, y, s);
-  return launch_ell<float>(A->M, A->K, A->ecol, A->eval, x, y, s);
+  const bool xcd = !(A->params.flags & SPMV_FLAG_LINEAR);
+  if (A->dt == SPMV_F64) return launch_ell<double>(A->M, A->K, A->ecol, A->eval, x, y, xcd, s);
+  return launch_ell<float>(A->M, A->K, A->ecol, A->eval, x, y, xcd, s);
 }
 
 static spmv_status_t check_cap(const spmv_mat_s* A, int64_t bytes, const char* what) {
@@ -325,27 +403,29 @@ __global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const in
   const int32_t* cc = scol + base + p;
   const T* vv = sval + base + p;
   double sa[4] = {0.0, 0.0, 0.0, 0.0};
-  int64_t k = k0;
-  for (; k + 7 < k1; k += 8) {
-    int32_t c8[8];
-    T v8[8];
+  {
+    int64_t k = k0;
+    for (; k + 7 < k1; k += 8) {
+      int32_t c8[8];
+      T v8[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c8[u] = ldnt(cc + (k + u) * C);
+      for (int u = 0; u < 8; ++u) c8[u] = ldnt(cc + (k + u) * C);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v8[u] = ldnt(vv + (k + u) * C);
-    issue_fence();
-    T x8[8];
+      for (int u = 0; u < 8; ++u) v8[u] = ldnt(vv + (k + u) * C);
+      issue_fence();
+      T x8[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x8[u] = ld32(x, (uint32_t)(c8[u] >= 0 ? c8[u] : 0));
-    issue_fence();
+      for (int u = 0; u < 8; ++u) x8[u] = ld32(x, (uint32_t)(c8[u] >= 0 ? c8[u] : 0));
+      issue_fence();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) sa[u & 3] += c8[u] >= 0 ? (double)v8[u] * (double)x8[u] : 0.0;
-  }
-  for (; k < k1; ++k) {
-    const int32_t c0 = ldnt(cc + k * C);
-    const T v0 = ldnt(vv + k * C);
-    const T x0 = x[c0 >= 0 ? c0 : 0];
-    sa[0] += c0 >= 0 ? (double)v0 * (double)x0 : 0.0;
+      for (int u = 0; u < 8; ++u) sa[u & 3] += c8[u] >= 0 ? (double)v8[u] * (double)x8[u] : 0.0;
+    }
+    for (; k < k1; ++k) {
+      const int32_t c0 = ldnt(cc + k * C);
+      const T v0 = ldnt(vv + k * C);
+      const T x0 = x[c0 >= 0 ? c0 : 0];
+      sa[0] += c0 >= 0 ? (double)v0 * (double)x0 : 0.0;
+    }
   }
   const double s = (sa[0] + sa[1]) + (sa[2] + sa[3]);
   if (w <= SELL_KT) {
@@ -356,6 +436,44 @@ __global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const in
     part[it * C + p] = s;
   }
   }
+}
+
+// Narrow SELL (every chunk at most KC wide): one lane per stored row, one
+// pass over the chunks (no persistent loop), every slot's column and value
+// load in flight at once, then every gather, then the sum.  Places w..KC-1
+// of a chunk of width w reload slot w-1 (same address) and are masked.
+template <typename T, int LOGC, bool PERM, int KC>
+__global__ __launch_bounds__(BS) void k_sell_kc(int64_t M, int64_t nchunks, const int64_t* __restrict__ cs,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
+                                                const T* __restrict__ sval, const T* __restrict__ x,
+                                                T* __restrict__ y) {
+  constexpr int C = 1 << LOGC;
+  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t c = gid >> LOGC;
+  if (c >= nchunks) return;
+  const int p = (int)(gid & (C - 1));
+  const int64_t base = cs[c];
+  const int w = (int)((cs[c + 1] - base) >> LOGC);
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  if (w > 0) {
+    const int32_t* cc = scol + base + p;
+    const T* vv = sval + base + p;
+    int32_t cg[KC];
+    T vg[KC], xg[KC];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) cg[u] = ldnt32(cc, (uint32_t)((u < w ? u : w - 1) * C));
+#pragma unroll
+    for (int u = 0; u < KC; ++u) vg[u] = ldnt32(vv, (uint32_t)((u < w ? u : w - 1) * C));
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < KC; ++u) xg[u] = ld32(x, (uint32_t)(cg[u] >= 0 ? cg[u] : 0));
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < KC; ++u) sa[u & 3] += (u < w && cg[u] >= 0) ? (double)vg[u] * (double)xg[u] : 0.0;
+  }
+  const int64_t pos = c * C + p;
+  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+  if (r >= 0) y[r] = (T)((sa[0] + sa[1]) + (sa[2] + sa[3]));
 }
 
 // one thread per (wide chunk, stored row): y = sum of the slices' partials in order
@@ -374,8 +492,26 @@ __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restri
   if (r >= 0) y[r] = (T)s;
 }
 
+template <typename T, int LOGC, int KC>
+static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  const unsigned g = (unsigned)cdiv(A->nchunks << LOGC, BS);
+  if (A->perm)
+    launch(k_sell_kc<T, LOGC, true, KC>, g, BS, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
+           (const T*)x, (T*)y);
+  else
+    launch(k_sell_kc<T, LOGC, false, KC>, g, BS, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
+           (const T*)x, (T*)y);
+}
+
 template <typename T, int LOGC>
 static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (LOGC >= 3 && A->sell_maxw <= 32 && !(A->params.flags & SPMV_FLAG_SELL_SLICES)) {
+    if (A->sell_maxw <= 16)
+      launch_sell_kc<T, LOGC, 16>(A, x, y, s);
+    else
+      launch_sell_kc<T, LOGC, 32>(A, x, y, s);
+    return;
+  }
   const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nitems << LOGC, BS), resident_blocks(8));
   if (A->perm)
     launch(k_sell<T, LOGC, true>, g, BS, s, A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
@@ -444,9 +580,10 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   A->nchunks = cdiv(M, C);
   A->Mpad = A->nchunks * C;
   const unsigned g = grid_rows(std::max<int64_t>(M, A->Mpad));
+  int32_t maxlen = 0;
+  if (M > 0) SPMV_TRY(device_max_i32(src->ptr, M, 1, &maxlen, s));
+  A->sell_maxw = maxlen;
   if (sigma > 1 && M > 0) {
-    int32_t maxlen = 0;
-    SPMV_TRY(device_max_i32(src->ptr, M, 1, &maxlen, s));
     DTmp k1, k2, v1, v2;
     SPMV_TRY(k1.alloc(sizeof(uint64_t) * M));
     SPMV_TRY(k2.alloc(sizeof(uint64_t) * M));
@@ -668,7 +805,7 @@ __global__ __launch_bounds__(BS) void k_coo(const int32_t* __restrict__ blk, con
 template <typename T>
 static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   if (A->M == 0) return SPMV_OK;
-  SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, s));
+  SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, !(A->params.flags & SPMV_FLAG_LINEAR), s));
   if (A->ncoo > 0) {
     launch(k_coo<T>, (unsigned)A->ncoo_blk, BS, s, A->coo_blk, A->crow, A->ccol, (const T*)A->cval, (const T*)x, (T*)y);
     SPMV_LAUNCH_CHECK();

@@ -81,9 +81,25 @@ __global__ void k_feat_rows(int64_t M, const int32_t* ptr, const int32_t* col, F
   }
 }
 
-__global__ void k_feat_hist(int64_t M, const int32_t* ptr, int32_t* hist) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[ptr[i + 1] - ptr[i]], 1);
+// Row-length histogram.  Regular matrices put most rows in a handful of
+// bins, so each block counts lengths below HB in LDS and adds its non-zero
+// bins to the global histogram once; only longer rows go to global atomics.
+constexpr int HB = 4096;
+
+__global__ __launch_bounds__(BS) void k_feat_hist(int64_t M, int64_t nv, const int32_t* ptr, int32_t* hist) {
+  __shared__ int32_t sh[HB];
+  for (int b = threadIdx.x; b < HB; b += BS) sh[b] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t len = ptr[i + 1] - ptr[i];
+    if (len < HB)
+      atomicAdd(&sh[len], 1);
+    else
+      atomicAdd(&hist[len], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < HB && b < nv; b += BS)
+    if (sh[b]) atomicAdd(&hist[b], sh[b]);
 }
 
 // Gini numerator: rows of length v fill sorted positions a_v+1 .. a_v+c_v
@@ -126,35 +142,88 @@ __global__ void k_feat_final(int64_t M, int64_t N, int64_t nnz, const FeatAcc* a
   f[11] = nnz > 0 ? (double)(long long)acc->gini / (Md * nz) : 0.0;
 }
 
+// Exclusive scan of the histogram by one workgroup (nv is at most the
+// longest row + 1, so this is short), carrying the running total in int64.
+__global__ __launch_bounds__(BS) void k_feat_below(int64_t nv, const int32_t* hist, int64_t* below) {
+  __shared__ int64_t wsum[BS / WAVE];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = __lane_id(), w = threadIdx.x / WAVE;
+  for (int64_t c0 = 0; c0 < nv; c0 += BS) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nv ? hist[i] : 0;
+    int64_t inc = v;  // inclusive scan inside the wave
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int64_t u = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += u;
+    }
+    if (lane == WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    int64_t before = carry;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    if (i < nv) below[i] = before + inc - v;
+    __syncthreads();
+    if (threadIdx.x == BS - 1) carry = before + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) below[nv] = carry;
+}
+
+// Feature workspace: kept for the life of the process (grow-only) and used
+// under a lock, so a features call allocates nothing after the first.
+static std::mutex g_feat_mu;
+static void* g_feat_ws = nullptr;
+static size_t g_feat_bytes = 0;
+
 spmv_status_t features(spmv_mat_s* A, double* out_host, hipStream_t s) {
   if (A->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_INVALID_ARG, "features need a CSR handle");
   const int64_t M = A->M;
-  DTmp acc, fo;
-  SPMV_TRY(acc.alloc(sizeof(FeatAcc)));
-  SPMV_TRY(fo.alloc(12 * sizeof(double)));
-  k_feat_init<<<1, 1, 0, s>>>(acc.as<FeatAcc>());
+  std::lock_guard<std::mutex> lock(g_feat_mu);
+  auto reserve = [&](size_t bytes) -> spmv_status_t {
+    if (bytes <= g_feat_bytes) return SPMV_OK;
+    if (g_feat_ws) {
+      SPMV_HIP(hipDeviceSynchronize());
+      dfree(g_feat_ws);
+      g_feat_ws = nullptr;
+      g_feat_bytes = 0;
+    }
+    SPMV_TRY(dmalloc(&g_feat_ws, bytes));
+    g_feat_bytes = bytes;
+    return SPMV_OK;
+  };
+  constexpr size_t SMALL = 256;  // FeatAcc + 12 doubles
+  SPMV_TRY(reserve(SMALL + 4096));
+  FeatAcc* acc = (FeatAcc*)g_feat_ws;
+  double* fo = (double*)((char*)g_feat_ws + 128);
+  k_feat_init<<<1, 1, 0, s>>>(acc);
   SPMV_LAUNCH_CHECK();
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M, BS), 2048));
   if (M) {
-    k_feat_rows<<<g, BS, 0, s>>>(M, A->ptr, A->col, acc.as<FeatAcc>());
+    k_feat_rows<<<g, BS, 0, s>>>(M, A->ptr, A->col, acc);
     SPMV_LAUNCH_CHECK();
     FeatAcc h;
-    SPMV_TRY(copy_to_host(&h, acc.p, sizeof(FeatAcc), s));
+    SPMV_TRY(copy_to_host(&h, acc, sizeof(FeatAcc), s));
     const int64_t nv = (int64_t)h.maxlen + 1;
-    DTmp hist, below;
-    SPMV_TRY(hist.alloc(sizeof(int32_t) * nv));
-    SPMV_TRY(below.alloc(sizeof(int64_t) * (nv + 1)));
-    SPMV_HIP(hipMemsetAsync(hist.p, 0, sizeof(int32_t) * nv, s));
-    k_feat_hist<<<g, BS, 0, s>>>(M, A->ptr, hist.as<int32_t>());
+    const size_t hb = ((size_t)nv * sizeof(int32_t) + 255) / 256 * 256;
+    SPMV_TRY(reserve(SMALL + hb + sizeof(int64_t) * (nv + 1)));
+    acc = (FeatAcc*)g_feat_ws;
+    fo = (double*)((char*)g_feat_ws + 128);
+    int32_t* hist = (int32_t*)((char*)g_feat_ws + SMALL);
+    int64_t* below = (int64_t*)((char*)g_feat_ws + SMALL + hb);
+    SPMV_HIP(hipMemcpyAsync(acc, &h, sizeof(FeatAcc), hipMemcpyHostToDevice, s));  // the buffer may have moved
+    SPMV_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * nv, s));
+    k_feat_hist<<<(unsigned)std::min<int64_t>(g, 512), BS, 0, s>>>(M, nv, A->ptr, hist);
     SPMV_LAUNCH_CHECK();
-    SPMV_TRY(scan_i32_to_i64(hist.as<int32_t>(), below.as<int64_t>(), nv, s));
+    k_feat_below<<<1, BS, 0, s>>>(nv, hist, below);
+    SPMV_LAUNCH_CHECK();
     const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(nv, BS), 2048));
-    k_feat_gini<<<gv, BS, 0, s>>>(nv, M, hist.as<int32_t>(), below.as<int64_t>(), acc.as<FeatAcc>());
+    k_feat_gini<<<gv, BS, 0, s>>>(nv, M, hist, below, acc);
     SPMV_LAUNCH_CHECK();
   }
-  k_feat_final<<<1, 1, 0, s>>>(M, A->N, A->nnz, acc.as<FeatAcc>(), fo.as<double>());
+  k_feat_final<<<1, 1, 0, s>>>(M, A->N, A->nnz, acc, fo);
   SPMV_LAUNCH_CHECK();
-  return copy_to_host(out_host, fo.p, 12 * sizeof(double), s);
+  return copy_to_host(out_host, fo, 12 * sizeof(double), s);
 }
 
 // ==================================================================== MLP

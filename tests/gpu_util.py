@@ -40,12 +40,17 @@ FORMAT_CONFIGS = [
     ("csr", {"csr_lanes_per_row": 1}),
     ("csr", {"csr_lanes_per_row": 4}),
     ("csr", {"csr_lanes_per_row": 64}),
+    ("csr", {"flags": 2}),
+    ("csr", {"flags": 4}),
     ("csr5", {}),
     ("csr5", {"csr5_sigma": 4}),
     ("csr5", {"csr5_sigma": 32}),
     ("csr5", {"csr5_omega": 16, "csr5_sigma": 3}),
     ("ell", {}),
+    ("ell", {"flags": 4}),
     ("sell", {}),
+    ("sell", {"flags": 8}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1}),
     ("sell", {"sell_C": 8, "sell_sigma": 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 16384}),
     ("hyb", {}),
