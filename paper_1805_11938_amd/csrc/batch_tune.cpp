@@ -85,7 +85,8 @@ spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* 
     SPMV_HIP(hipMemcpy(b->xy, ptrs.data(), sizeof(void*) * 2 * b->n, hipMemcpyHostToDevice));
     b->last = ptrs;
   }
-  const int grid = (int)std::min<int64_t>(std::max<int64_t>(b->nitems, 1), resident_blocks(6));
+  if (b->nitems > INT32_MAX) return fail(SPMV_ERR_TOO_LARGE, "batch of %lld row blocks", (long long)b->nitems);
+  const int grid = (int)std::max<int64_t>(b->nitems, 1);  // one workgroup per row block
   return launch_batched(b->dt, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st);
 }
 

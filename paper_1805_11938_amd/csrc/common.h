@@ -170,6 +170,8 @@ struct spmv_mat_s {
   int32_t c5_tail_row = 0;       // row holding the first tail entry (M when there is no tail)
   int has_empty = 0;
   int32_t* nzrow = nullptr;      // non-empty rows, ascending (only when has_empty)
+  int32_t* erows = nullptr;      // empty rows, ascending (only when has_empty)
+  int64_t nerows = 0;
   int32_t* tile_nzbase = nullptr;
   int64_t nchains = 0;
   int32_t* chains = nullptr;     // (row, t_begin, t_end) triples for the carry fix-up

@@ -534,8 +534,7 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
 // The item table, built once when the batch is created, holds each item's
 // matrix arrays, row range and nonzero range, so a workgroup issues its
 // column and value loads right after reading one record (no search over
-// the matrices, no dependent row-pointer loads).  A fixed grid strides over
-// the table.
+// the matrices, no dependent row-pointer loads).
 struct BatchItem {
   const int32_t* ptr;
   const int32_t* col;
@@ -566,11 +565,13 @@ __global__ __launch_bounds__(BS) void k_csr_batched(int64_t nitems, const BatchI
                                                     const void* const* __restrict__ xs, void* const* __restrict__ ys) {
   __shared__ double prod[CSR_CAP];
   __shared__ int32_t sptr[CSR_RCAP + 1];
-  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
-    const BatchItem it = items[i];
-    csr_rows_block<T>(it.r0, it.r1, it.k0, it.k1, it.ptr, it.col, (const T*)it.val, (const T*)xs[it.m],
-                      (T*)ys[it.m], prod, sptr);
-  }
+  // one workgroup per item; each XCD takes a contiguous range of items, so
+  // the blocks of one matrix (which share its x) meet in one L2
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x);
+  if (i >= nitems) return;
+  const BatchItem it = items[i];
+  csr_rows_block<T>(it.r0, it.r1, it.k0, it.k1, it.ptr, it.col, (const T*)it.val, (const T*)xs[it.m],
+                    (T*)ys[it.m], prod, sptr);
 }
 
 spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s) {

@@ -128,6 +128,18 @@ __global__ void k_c5_nzrow(int64_t M, const int32_t* ptr, const int32_t* rank, i
     if (ptr[r + 1] > ptr[r]) nzrow[rank[r]] = (int32_t)r;
 }
 
+__global__ void k_c5_erows(int64_t M, const int32_t* ptr, const int32_t* rank, int32_t* erows) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x)
+    if (ptr[r + 1] == ptr[r]) erows[r - rank[r]] = (int32_t)r;
+}
+
+// y = 0 on the empty rows (the tiles write only rows that own entries)
+template <typename T>
+__global__ void k_c5_zero(int64_t n, const int32_t* __restrict__ erows, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[erows[i]] = (T)0;
+}
+
 __global__ void k_c5_nzbase(int64_t T, const int32_t* tile_ptr, const int32_t* rank, int32_t* base) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (int64_t)gridDim.x * blockDim.x)
     base[t] = rank[tile_ptr[t]];
@@ -236,6 +248,10 @@ spmv_status_t convert_csr5(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     SPMV_TRY(mat_alloc(A, (void**)&A->tile_nzbase, sizeof(int32_t) * std::max<int64_t>(T, 1)));
     k_c5_nzrow<<<grid_n(M), BS, 0, s>>>(M, src->ptr, rank.as<int32_t>(), A->nzrow);
     SPMV_LAUNCH_CHECK();
+    A->nerows = M - nnzrows;
+    SPMV_TRY(mat_alloc(A, (void**)&A->erows, sizeof(int32_t) * A->nerows));
+    k_c5_erows<<<grid_n(M), BS, 0, s>>>(M, src->ptr, rank.as<int32_t>(), A->erows);
+    SPMV_LAUNCH_CHECK();
     if (T) {
       k_c5_nzbase<<<grid_n(T), BS, 0, s>>>(T, A->tile_ptr, rank.as<int32_t>(), A->tile_nzbase);
       SPMV_LAUNCH_CHECK();
@@ -268,7 +284,7 @@ spmv_status_t convert_csr5(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     SPMV_HIP(hipStreamSynchronize(s));
   }
   A->bytes_fmt = nnz * (4 + A->sv) + T * omega * 4 + (T + 1) * 4 + A->N * A->sv + A->M * A->sv +
-                 (A->has_empty ? (int64_t)nnzrows * 8 + T * 4 : 0);
+                 (A->has_empty ? (int64_t)nnzrows * 8 + T * 4 + A->nerows * 4 : 0);
   SPMV_HIP(hipStreamSynchronize(s));
   return SPMV_OK;
 }
@@ -313,10 +329,7 @@ __device__ __forceinline__ void c5_write(const C5Args& a, int64_t t, int64_t row
     y[row0 + j] = (T)s;
     return;
   }
-  const int64_t row = a.nzrow[nzb + j];
-  y[row] = (T)s;
-  const int64_t prev = (nzb + j == 0) ? -1 : a.nzrow[nzb + j - 1];
-  for (int64_t r = prev + 1; r < row; ++r) y[r] = (T)0;
+  y[a.nzrow[nzb + j]] = (T)s;  // empty rows are zeroed by k_c5_zero
 }
 
 // The tail (entries past the last full tile) in CSR order: its leading
@@ -484,6 +497,10 @@ static spmv_status_t run_csr5_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) 
   a.tail_row = A->c5_tail_row;
   a.carry = A->carry;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(a.nb_main, resident_blocks(8)));
+  if (A->nerows > 0) {
+    launch(k_c5_zero<T>, (unsigned)std::min<int64_t>(cdiv(A->nerows, BS), 4096), BS, s, A->nerows, A->erows, y);
+    SPMV_LAUNCH_CHECK();
+  }
   if (A->has_empty) launch_c5<T, true>(a, grid, (const T*)A->val, x, y, s);
   else launch_c5<T, false>(a, grid, (const T*)A->val, x, y, s);
   SPMV_LAUNCH_CHECK();

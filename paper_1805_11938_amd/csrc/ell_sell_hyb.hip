@@ -448,8 +448,10 @@ __global__ __launch_bounds__(BS) void k_sell_kc(int64_t M, int64_t nchunks, cons
                                                 const T* __restrict__ sval, const T* __restrict__ x,
                                                 T* __restrict__ y) {
   constexpr int C = 1 << LOGC;
-  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
-  const int64_t c = gid >> LOGC;
+  // each XCD takes a contiguous range of chunks (neighbouring rows share x in its L2)
+  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+  // C = 64: one chunk per wave, so its offsets are scalar loads
+  const int64_t c = LOGC == 6 ? (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(gid >> 6)) : gid >> LOGC;
   if (c >= nchunks) return;
   const int p = (int)(gid & (C - 1));
   const int64_t base = cs[c];
@@ -506,10 +508,47 @@ static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s)
 template <typename T, int LOGC>
 static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   if (LOGC >= 3 && A->sell_maxw <= 32 && !(A->params.flags & SPMV_FLAG_SELL_SLICES)) {
-    if (A->sell_maxw <= 16)
+    if (LOGC == 6) {  // one chunk per wave: instantiated for the exact widest chunk
+      switch (A->sell_maxw) {
+      case 1: launch_sell_kc<T, 6, 1>(A, x, y, s); break;
+      case 2: launch_sell_kc<T, 6, 2>(A, x, y, s); break;
+      case 3: launch_sell_kc<T, 6, 3>(A, x, y, s); break;
+      case 4: launch_sell_kc<T, 6, 4>(A, x, y, s); break;
+      case 5: launch_sell_kc<T, 6, 5>(A, x, y, s); break;
+      case 6: launch_sell_kc<T, 6, 6>(A, x, y, s); break;
+      case 7: launch_sell_kc<T, 6, 7>(A, x, y, s); break;
+      case 8: launch_sell_kc<T, 6, 8>(A, x, y, s); break;
+      case 9: launch_sell_kc<T, 6, 9>(A, x, y, s); break;
+      case 10: launch_sell_kc<T, 6, 10>(A, x, y, s); break;
+      case 11: launch_sell_kc<T, 6, 11>(A, x, y, s); break;
+      case 12: launch_sell_kc<T, 6, 12>(A, x, y, s); break;
+      case 13: launch_sell_kc<T, 6, 13>(A, x, y, s); break;
+      case 14: launch_sell_kc<T, 6, 14>(A, x, y, s); break;
+      case 15: launch_sell_kc<T, 6, 15>(A, x, y, s); break;
+      case 16: launch_sell_kc<T, 6, 16>(A, x, y, s); break;
+      case 17: launch_sell_kc<T, 6, 17>(A, x, y, s); break;
+      case 18: launch_sell_kc<T, 6, 18>(A, x, y, s); break;
+      case 19: launch_sell_kc<T, 6, 19>(A, x, y, s); break;
+      case 20: launch_sell_kc<T, 6, 20>(A, x, y, s); break;
+      case 21: launch_sell_kc<T, 6, 21>(A, x, y, s); break;
+      case 22: launch_sell_kc<T, 6, 22>(A, x, y, s); break;
+      case 23: launch_sell_kc<T, 6, 23>(A, x, y, s); break;
+      case 24: launch_sell_kc<T, 6, 24>(A, x, y, s); break;
+      case 25: launch_sell_kc<T, 6, 25>(A, x, y, s); break;
+      case 26: launch_sell_kc<T, 6, 26>(A, x, y, s); break;
+      case 27: launch_sell_kc<T, 6, 27>(A, x, y, s); break;
+      case 28: launch_sell_kc<T, 6, 28>(A, x, y, s); break;
+      case 29: launch_sell_kc<T, 6, 29>(A, x, y, s); break;
+      case 30: launch_sell_kc<T, 6, 30>(A, x, y, s); break;
+      case 31: launch_sell_kc<T, 6, 31>(A, x, y, s); break;
+      case 32: launch_sell_kc<T, 6, 32>(A, x, y, s); break;
+        default: launch_sell_kc<T, 6, 32>(A, x, y, s); break;  // maxw == 0: nothing to load
+      }
+    } else if (A->sell_maxw <= 16) {
       launch_sell_kc<T, LOGC, 16>(A, x, y, s);
-    else
+    } else {
       launch_sell_kc<T, LOGC, 32>(A, x, y, s);
+    }
     return;
   }
   const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nitems << LOGC, BS), resident_blocks(8));

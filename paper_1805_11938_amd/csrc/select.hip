@@ -31,7 +31,14 @@ __global__ void k_feat_init(FeatAcc* a) {
   a->sum = a->sumsq = a->gini = 0;
 }
 
-__global__ void k_feat_rows(int64_t M, const int32_t* ptr, const int32_t* col, FeatAcc* acc) {
+// Per-block partials (no contended atomics): minimum, maximum and the
+// bandwidth of the block's rows, their length sum and sum of squares.
+struct FeatPart {
+  int32_t minlen, maxlen, band, pad;
+  unsigned long long sum, sumsq;
+};
+
+__global__ __launch_bounds__(BS) void k_feat_rows(int64_t M, const int32_t* ptr, const int32_t* col, FeatPart* part) {
   __shared__ int32_t smin[BS / WAVE], smax[BS / WAVE], sband[BS / WAVE];
   __shared__ unsigned long long ssum[BS / WAVE], ssq[BS / WAVE];
   int32_t mn = INT32_MAX, mx = 0, band = 0;
@@ -73,11 +80,63 @@ __global__ void k_feat_rows(int64_t M, const int32_t* ptr, const int32_t* col, F
       sum += ssum[q];
       sq += ssq[q];
     }
-    atomicMin(&acc->minlen, mn);
-    atomicMax(&acc->maxlen, mx);
-    atomicMax(&acc->band, band);
-    atomicAdd(&acc->sum, sum);
-    atomicAdd(&acc->sumsq, sq);
+    FeatPart p;
+    p.minlen = mn;
+    p.maxlen = mx;
+    p.band = band;
+    p.pad = 0;
+    p.sum = sum;
+    p.sumsq = sq;
+    part[blockIdx.x] = p;
+  }
+}
+
+// One workgroup folds the per-block partials into the accumulator.
+__global__ __launch_bounds__(BS) void k_feat_fold(int nparts, const FeatPart* part, FeatAcc* acc) {
+  __shared__ int32_t smin[BS / WAVE], smax[BS / WAVE], sband[BS / WAVE];
+  __shared__ unsigned long long ssum[BS / WAVE], ssq[BS / WAVE];
+  int32_t mn = INT32_MAX, mx = 0, band = 0;
+  unsigned long long sum = 0, sq = 0;
+  for (int i = threadIdx.x; i < nparts; i += BS) {
+    const FeatPart p = part[i];
+    mn = p.minlen < mn ? p.minlen : mn;
+    mx = p.maxlen > mx ? p.maxlen : mx;
+    band = p.band > band ? p.band : band;
+    sum += p.sum;
+    sq += p.sumsq;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64), c = __shfl_xor(band, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+    band = c > band ? c : band;
+    sum += __shfl_xor(sum, o, 64);
+    sq += __shfl_xor(sq, o, 64);
+  }
+  const int w = threadIdx.x / WAVE;
+  if (__lane_id() == 0) {
+    smin[w] = mn;
+    smax[w] = mx;
+    sband[w] = band;
+    ssum[w] = sum;
+    ssq[w] = sq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < BS / WAVE; ++q) {
+      mn = smin[q] < mn ? smin[q] : mn;
+      mx = smax[q] > mx ? smax[q] : mx;
+      band = sband[q] > band ? sband[q] : band;
+      sum += ssum[q];
+      sq += ssq[q];
+    }
+    acc->minlen = mn;
+    acc->maxlen = mx;
+    acc->band = band;
+    acc->pad = 0;
+    acc->sum = sum;
+    acc->sumsq = sq;
+    acc->gini = 0;
   }
 }
 
@@ -192,15 +251,19 @@ spmv_status_t features(spmv_mat_s* A, double* out_host, hipStream_t s) {
     g_feat_bytes = bytes;
     return SPMV_OK;
   };
-  constexpr size_t SMALL = 256;  // FeatAcc + 12 doubles
+  constexpr int MAXG = 2048;                                // feature blocks
+  constexpr size_t SMALL = 256 + MAXG * sizeof(FeatPart);  // FeatAcc, 12 doubles, per-block partials
   SPMV_TRY(reserve(SMALL + 4096));
   FeatAcc* acc = (FeatAcc*)g_feat_ws;
   double* fo = (double*)((char*)g_feat_ws + 128);
+  FeatPart* parts = (FeatPart*)((char*)g_feat_ws + 256);
   k_feat_init<<<1, 1, 0, s>>>(acc);
   SPMV_LAUNCH_CHECK();
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M, BS), 2048));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M, BS), MAXG));
   if (M) {
-    k_feat_rows<<<g, BS, 0, s>>>(M, A->ptr, A->col, acc);
+    k_feat_rows<<<g, BS, 0, s>>>(M, A->ptr, A->col, parts);
+    SPMV_LAUNCH_CHECK();
+    k_feat_fold<<<1, BS, 0, s>>>((int)g, parts, acc);
     SPMV_LAUNCH_CHECK();
     FeatAcc h;
     SPMV_TRY(copy_to_host(&h, acc, sizeof(FeatAcc), s));
