@@ -332,21 +332,24 @@ __device__ __forceinline__ void c5_write(const C5Args& a, int64_t t, int64_t row
   y[a.nzrow[nzb + j]] = (T)s;  // empty rows are zeroed by k_c5_zero
 }
 
-// The tail (entries past the last full tile) in CSR order: its leading
-// continuation goes to carry[ntiles]; rows starting in it are summed here.
+// The tail (entries past the last full tile) in CSR order.  Its leading
+// continuation goes to carry[ntiles] (the last workgroup); the rows that
+// start in it -- possibly many, when trailing rows are empty -- are spread
+// over every wave of the grid, one row per wave at a time.
 template <typename T>
 __device__ void c5_tail(const C5Args& a, const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
   __shared__ double sh[4];
   const int64_t TW = a.ntiles * (int64_t)a.omega * a.sigma;
-  const int t = threadIdx.x, w = t / WAVE, lane = __lane_id();
-  if (TW < a.nnz) {
+  const int t = threadIdx.x, lane = __lane_id();
+  if (blockIdx.x == gridDim.x - 1 && TW < a.nnz) {
     const int64_t rs = a.ptr[a.tail_row], re = a.ptr[a.tail_row + 1];
     if (rs < TW) {
       const double s = block_sum(row_dot(a.col, val, x, TW, re < a.nnz ? re : a.nnz, t, BS), sh);
       if (t == 0) a.carry[a.ntiles] = s;
     }
   }
-  for (int64_t r = a.tail_rlo + w; r < a.M; r += BS / WAVE) {
+  const int64_t nw = (int64_t)gridDim.x * (BS / WAVE);
+  for (int64_t r = a.tail_rlo + (int64_t)blockIdx.x * (BS / WAVE) + t / WAVE; r < a.M; r += nw) {
     const double s = group_sum<64>(row_dot(a.col, val, x, a.ptr[r], a.ptr[r + 1], lane, WAVE));
     if (lane == 0) y[r] = (T)s;
   }
@@ -431,8 +434,8 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
   if (seen) c5_write<T, EMPTY>(a, t, row0, nzb, cont, yoff + lf - 1, acc + S, y);
 }
 
-// Persistent: each lane group loops over tiles; the last workgroup then
-// sums the CSR-ordered tail.
+// Persistent: each lane group loops over tiles; then the grid sums the
+// CSR-ordered tail.
 template <typename T, int SIG, bool EMPTY, bool W64>
 __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val, const T* __restrict__ x,
                                              T* __restrict__ y) {
@@ -443,7 +446,7 @@ __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val
   const int64_t first = W64 ? (int64_t)blockIdx.x * tpb + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE)
                             : (int64_t)blockIdx.x * tpb + threadIdx.x / omega;
   for (int64_t t = first; t < a.ntiles; t += step) c5_tile<T, SIG, EMPTY, W64>(a, t, l, val, x, y);
-  if (blockIdx.x == gridDim.x - 1) c5_tail<T>(a, val, x, y);
+  c5_tail<T>(a, val, x, y);
 }
 
 template <typename T>

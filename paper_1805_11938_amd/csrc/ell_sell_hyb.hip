@@ -171,9 +171,10 @@ __global__ __launch_bounds__(BS) void k_ell2(int64_t M, int64_t K, const int32_t
 // each XCD takes a contiguous range of rows (the x window of neighbouring
 // rows stays in one L2).
 template <typename T, int KC, bool XCD>
-__global__ __launch_bounds__(BS) void k_ell_kc(int64_t M, const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                               const T* __restrict__ x, T* __restrict__ y) {
-  const int64_t i = (int64_t)(XCD ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * BS + threadIdx.x;
+__global__ __launch_bounds__(WAVE) void k_ell_kc(int64_t M, const int32_t* __restrict__ ecol,
+                                                 const T* __restrict__ eval, const T* __restrict__ x,
+                                                 T* __restrict__ y) {
+  const int64_t i = (int64_t)(XCD ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * WAVE + threadIdx.x;
   if (i >= M) return;
   int32_t c[KC];
   T v[KC], xv[KC];
@@ -195,38 +196,38 @@ template <typename T, bool XCD>
 static void launch_ell_kc(int64_t M, int32_t k, const int32_t* ecol, const void* eval, const void* x, void* y,
                           unsigned g, hipStream_t s) {
   switch (k) {
-    case 1: launch(k_ell_kc<T, 1, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 2: launch(k_ell_kc<T, 2, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 3: launch(k_ell_kc<T, 3, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 4: launch(k_ell_kc<T, 4, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 5: launch(k_ell_kc<T, 5, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 6: launch(k_ell_kc<T, 6, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 7: launch(k_ell_kc<T, 7, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 8: launch(k_ell_kc<T, 8, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 9: launch(k_ell_kc<T, 9, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 10: launch(k_ell_kc<T, 10, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 11: launch(k_ell_kc<T, 11, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 12: launch(k_ell_kc<T, 12, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 13: launch(k_ell_kc<T, 13, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 14: launch(k_ell_kc<T, 14, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 15: launch(k_ell_kc<T, 15, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 16: launch(k_ell_kc<T, 16, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 17: launch(k_ell_kc<T, 17, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 18: launch(k_ell_kc<T, 18, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 19: launch(k_ell_kc<T, 19, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 20: launch(k_ell_kc<T, 20, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 21: launch(k_ell_kc<T, 21, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 22: launch(k_ell_kc<T, 22, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 23: launch(k_ell_kc<T, 23, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 24: launch(k_ell_kc<T, 24, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 25: launch(k_ell_kc<T, 25, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 26: launch(k_ell_kc<T, 26, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 27: launch(k_ell_kc<T, 27, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 28: launch(k_ell_kc<T, 28, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 29: launch(k_ell_kc<T, 29, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 30: launch(k_ell_kc<T, 30, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 31: launch(k_ell_kc<T, 31, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
-    case 32: launch(k_ell_kc<T, 32, XCD>, g, BS, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 1: launch(k_ell_kc<T, 1, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 2: launch(k_ell_kc<T, 2, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 3: launch(k_ell_kc<T, 3, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 4: launch(k_ell_kc<T, 4, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 5: launch(k_ell_kc<T, 5, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 6: launch(k_ell_kc<T, 6, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 7: launch(k_ell_kc<T, 7, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 8: launch(k_ell_kc<T, 8, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 9: launch(k_ell_kc<T, 9, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 10: launch(k_ell_kc<T, 10, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 11: launch(k_ell_kc<T, 11, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 12: launch(k_ell_kc<T, 12, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 13: launch(k_ell_kc<T, 13, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 14: launch(k_ell_kc<T, 14, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 15: launch(k_ell_kc<T, 15, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 16: launch(k_ell_kc<T, 16, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 17: launch(k_ell_kc<T, 17, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 18: launch(k_ell_kc<T, 18, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 19: launch(k_ell_kc<T, 19, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 20: launch(k_ell_kc<T, 20, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 21: launch(k_ell_kc<T, 21, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 22: launch(k_ell_kc<T, 22, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 23: launch(k_ell_kc<T, 23, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 24: launch(k_ell_kc<T, 24, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 25: launch(k_ell_kc<T, 25, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 26: launch(k_ell_kc<T, 26, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 27: launch(k_ell_kc<T, 27, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 28: launch(k_ell_kc<T, 28, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 29: launch(k_ell_kc<T, 29, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 30: launch(k_ell_kc<T, 30, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 31: launch(k_ell_kc<T, 31, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
+    case 32: launch(k_ell_kc<T, 32, XCD>, g, WAVE, s, M, ecol, (const T*)eval, (const T*)x, (T*)y); break;
     default: break;
   }
 }
@@ -236,7 +237,7 @@ static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const
                                 bool xcd, hipStream_t s) {
   if (M == 0) return SPMV_OK;
   if (K >= 1 && K <= 32) {
-    const unsigned g = (unsigned)cdiv(M, BS);
+    const unsigned g = (unsigned)cdiv(M, WAVE);  // one wave per workgroup
     const int32_t k = (int32_t)K;
     if (xcd)
       launch_ell_kc<T, true>(M, k, ecol, eval, x, y, g, s);
@@ -443,13 +444,14 @@ __global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const in
 // load in flight at once, then every gather, then the sum.  Places w..KC-1
 // of a chunk of width w reload slot w-1 (same address) and are masked.
 template <typename T, int LOGC, bool PERM, int KC>
-__global__ __launch_bounds__(BS) void k_sell_kc(int64_t M, int64_t nchunks, const int64_t* __restrict__ cs,
-                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
-                                                const T* __restrict__ sval, const T* __restrict__ x,
-                                                T* __restrict__ y) {
+__global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t nchunks, const int64_t* __restrict__ cs,
+                                                  const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
+                                                  const T* __restrict__ sval, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
   constexpr int C = 1 << LOGC;
-  // each XCD takes a contiguous range of chunks (neighbouring rows share x in its L2)
-  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+  // one wave per workgroup (the finest unit the dispatcher balances); each
+  // XCD takes a contiguous range of chunks (neighbouring rows share x in its L2)
+  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVE + threadIdx.x;
   // C = 64: one chunk per wave, so its offsets are scalar loads
   const int64_t c = LOGC == 6 ? (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(gid >> 6)) : gid >> LOGC;
   if (c >= nchunks) return;
@@ -496,12 +498,12 @@ __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restri
 
 template <typename T, int LOGC, int KC>
 static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  const unsigned g = (unsigned)cdiv(A->nchunks << LOGC, BS);
+  const unsigned g = (unsigned)cdiv(A->nchunks << LOGC, WAVE);
   if (A->perm)
-    launch(k_sell_kc<T, LOGC, true, KC>, g, BS, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
+    launch(k_sell_kc<T, LOGC, true, KC>, g, WAVE, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
            (const T*)x, (T*)y);
   else
-    launch(k_sell_kc<T, LOGC, false, KC>, g, BS, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
+    launch(k_sell_kc<T, LOGC, false, KC>, g, WAVE, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
            (const T*)x, (T*)y);
 }
 
