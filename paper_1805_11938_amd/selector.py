@@ -302,6 +302,60 @@ def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB):
     return Ad.convert(fmt, **(params or {})), fmt, "exhaustive"
 
 
+def host_scale(F, lo=None, hi=None):
+    """The feature transform and min-max scaling of spmv_scale_features,
+    on the host, for the CPU classifiers below (returns X, lo, hi)."""
+    F = np.array(F, dtype=np.float64, copy=True)
+    logs = [0, 1, 2, 4, 5, 6, 7, 9, 10]
+    F[:, logs] = np.log2(1.0 + F[:, logs])
+    F[:, 3] = np.log2(np.maximum(F[:, 3], 2.0 ** -64))
+    if lo is None:
+        lo, hi = F.min(axis=0), F.max(axis=0)
+    span = hi - lo
+    X = np.zeros_like(F)
+    nz = span > 0
+    X[:, nz] = (F[:, nz] - lo[nz]) / span[nz]
+    return X, lo, hi
+
+
+def compare_classifiers(records, dtype="f64", test=None, seed=0):
+    """The paper's model comparison (Sec. V-D, Fig. 11) on this GPU's time
+    table: decision tree (the paper's model), Gaussian naive Bayes, 1-nearest
+    neighbour, logistic regression, random forest and their soft vote, each
+    trained on the same 80% and judged on the same held-out 20% as the MLP.
+    CPU (scikit-learn); an offline evaluation, not part of the run path."""
+    from sklearn.ensemble import RandomForestClassifier, VotingClassifier
+    from sklearn.linear_model import LogisticRegression
+    from sklearn.naive_bayes import GaussianNB
+    from sklearn.neighbors import KNeighborsClassifier
+    from sklearn.tree import DecisionTreeClassifier
+    rs = [r for r in records if r["dtype"] == dtype]
+    if test is None:
+        test = split(records)
+    tr = [r for r in rs if r["index"] not in test]
+    te = [r for r in rs if r["index"] in test]
+    Xtr, lo, hi = host_scale([r["features"] for r in tr])
+    Xte, _, _ = host_scale([r["features"] for r in te], lo, hi)
+    ytr = np.array([label_of(r["times_ms"]) for r in tr])
+    T = [r["times_ms"] for r in te]
+    models = {
+        "dtc": DecisionTreeClassifier(random_state=seed),
+        "gnb": GaussianNB(),
+        "knn1": KNeighborsClassifier(n_neighbors=1),
+        "lr": LogisticRegression(max_iter=2000),
+        "rfc": RandomForestClassifier(n_estimators=100, random_state=seed),
+    }
+    models["vote"] = VotingClassifier([(k, v) for k, v in models.items() if k != "knn1"], voting="soft")
+    out = {}
+    for name, m in models.items():
+        m.fit(Xtr, ytr)
+        pred = m.predict(Xte)
+        ev = evaluate(T, pred)
+        out[name] = {"frac": ev["frac"], "geo": ev["geo"], "accuracy": ev["accuracy"]}
+    out["fixed_csr"] = {"frac": evaluate(T, [0] * len(T))["frac"]}
+    return out
+
+
 PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags"), "csr5": ("csr5_omega", "csr5_sigma"), "ell": (),
               "sell": ("sell_C", "sell_sigma"), "hyb": ("hyb_K",)}
 
@@ -335,12 +389,18 @@ def main(argv=None):
     t.add_argument("--dataset", required=True)
     t.add_argument("--out-dir", default=DATA_DIR)
     t.add_argument("--epochs", type=int, default=500)
+    cp = sub.add_parser("compare")
+    cp.add_argument("--dataset", required=True)
     m = sub.add_parser("merge")
     m.add_argument("out")
     m.add_argument("parts", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "collect":
         collect(a.start, a.stop, a.out, budget_s=a.budget)
+    elif a.cmd == "compare":
+        recs = load(a.dataset)
+        for dt in ("f64", "f32"):
+            print(dt, json.dumps(compare_classifiers(recs, dt)))
     elif a.cmd == "merge":
         log(f"[merge] {merge(a.out, a.parts)} records")
     else:
