@@ -185,7 +185,8 @@ spmv_status_t spmv_batch_run_timed(spmv_batch_t b, const void* const* x, void* c
 spmv_status_t spmv_time(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, int warmup, int min_reps,
                         int max_reps, double rel_ci, int64_t scrub_bytes, spmv_stream_t s, double out[5]);
 
-/* Enqueue the cache scrub on s (writes scrub_bytes of a library buffer). */
+/* Enqueue the cache scrub on s (reads scrub_bytes of a library buffer, so
+ * the caches hold clean lines of it afterwards). */
 spmv_status_t spmv_scrub(int64_t scrub_bytes, spmv_stream_t s);
 
 /* Device-to-device copy probe: returns the GB/s of a plain copy kernel
@@ -194,9 +195,14 @@ spmv_status_t spmv_copy_probe(int64_t bytes, int reps, spmv_stream_t s, double* 
 
 /* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: V;
  * HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma) on x/y and write the
- * fastest into *inout.  ms_out (optional) receives the best median. */
+ * fastest into *inout.  ms_out (optional) receives the best median.  The
+ * result is cached for the life of the process, keyed by a 64-bit hash of
+ * the sparsity structure (ptr, col), the shape, dtype, format and byte cap:
+ * a second call for the same structure returns the cached choice without
+ * timing (spmv_autotune_cache_clear empties the cache). */
 spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void* y, int64_t scrub_bytes, int reps,
                             spmv_params_t* inout, double* ms_out, spmv_stream_t s);
+void spmv_autotune_cache_clear(void);
 
 /* ------------------------------------------------------------ selection */
 

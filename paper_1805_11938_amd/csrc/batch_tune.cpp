@@ -1,6 +1,9 @@
 // Batched launch, SpMM entry point and the autotuner (host side).
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 #include "common.h"
 
@@ -108,6 +111,13 @@ void spmv_batch_free(spmv_batch_t b) {
 // Exhaustive search over a small grid per format; each candidate is
 // converted and timed with the same protocol as spmv_time (median of the
 // confidence-interval rule).  Only performance depends on the choice.
+// Results are cached per (structure hash, shape, dtype, format, byte cap)
+// for the life of the process: tuning depends on the sparsity structure,
+// not on the values.
+typedef std::tuple<uint64_t, int64_t, int64_t, int64_t, int, int, int64_t> TuneKey;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<spmv_params_t, double>> g_tune_cache;
+
 spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void* y, int64_t scrub_bytes, int reps,
                             spmv_params_t* inout, double* ms_out, spmv_stream_t s) {
   if (!csr || csr->fmt != SPMV_FMT_CSR || !inout) return fail(SPMV_ERR_INVALID_ARG, "autotune arguments");
@@ -116,6 +126,18 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
   hipStream_t st = hs(s);
   spmv_params_t base;
   resolve_params(inout, &base);
+  uint64_t h = 0;
+  SPMV_TRY(structure_hash(csr, &h, st));
+  const TuneKey key(h, csr->M, csr->N, csr->nnz, (int)csr->dt, (int)fmt, base.max_bytes);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *inout = it->second.first;
+      if (ms_out) *ms_out = it->second.second;
+      return SPMV_OK;
+    }
+  }
   std::vector<spmv_params_t> cand;
   auto add = [&](auto&& f) {
     spmv_params_t p = base;
@@ -180,7 +202,14 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
   if (!any) return fail(SPMV_ERR_TOO_LARGE, "no candidate of format %d fits the byte cap", (int)fmt);
   *inout = bestp;
   if (ms_out) *ms_out = best;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = std::make_pair(bestp, best);
   return SPMV_OK;
+}
+
+void spmv_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache.clear();
 }
 
 }  // extern "C"

@@ -64,6 +64,7 @@ int64_t default_max_bytes();
 // Workgroups that fit on the device at once when each CU holds per_cu of them
 // (persistent kernels size their grid with it).
 int64_t resident_blocks(int per_cu);
+spmv_status_t structure_hash(const spmv_mat_s* A, uint64_t* out, hipStream_t s);
 
 // Kernel-bound timing.  While a RunTiming is armed on the calling thread,
 // every kernel of a run path is launched through hipExtLaunchKernel: the

@@ -362,4 +362,44 @@ spmv_status_t radix_sort_pairs(uint64_t** keys, uint32_t** vals, uint64_t* keys_
   return SPMV_OK;
 }
 
+// ------------------------------------------------------ structure hash
+// Order-independent 64-bit fingerprint of a CSR structure (ptr and col):
+// the sum mod 2^64 of SplitMix64 finalisers of (position, value) pairs.
+// Used to key the autotuner's cache; values do not affect performance and
+// are not hashed.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(BS) void k_struct_hash(int64_t M, int64_t nnz, const int32_t* ptr, const int32_t* col,
+                                                    unsigned long long* part) {
+  __shared__ unsigned long long sh[BS / WAVE];
+  unsigned long long h = 0;
+  const int64_t n = M + 1 + nnz;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t v = i <= M ? (uint64_t)(uint32_t)ptr[i] : (uint64_t)(uint32_t)col[i - M - 1];
+    h += mix64((uint64_t)i * 0x9E3779B97F4A7C15ull ^ (v << 1) ^ (i <= M ? 1ull : 0ull));
+  }
+  for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+  if (__lane_id() == 0) sh[threadIdx.x / WAVE] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+spmv_status_t structure_hash(const spmv_mat_s* A, uint64_t* out, hipStream_t s) {
+  constexpr int G = 512;
+  DTmp part;
+  SPMV_TRY(part.alloc(sizeof(unsigned long long) * G));
+  k_struct_hash<<<G, BS, 0, s>>>(A->M, A->nnz, A->ptr, A->col, part.as<unsigned long long>());
+  SPMV_LAUNCH_CHECK();
+  unsigned long long h[G];
+  SPMV_TRY(copy_to_host(h, part.p, sizeof(h), s));
+  uint64_t t = 0;
+  for (int i = 0; i < G; ++i) t += h[i];
+  *out = t;
+  return SPMV_OK;
+}
+
 }  // namespace spmv

@@ -61,7 +61,7 @@ EXPORTED = [
     "spmv_autotune", "spmv_features", "spmv_model_create", "spmv_model_load", "spmv_model_save",
     "spmv_model_params", "spmv_model_free", "spmv_select", "spmv_mlp_forward", "spmv_mlp_backward", "spmv_mlp_adam",
     "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train", "spmv_run_timed", "spmv_spmm_timed",
-    "spmv_batch_run_timed",
+    "spmv_batch_run_timed", "spmv_autotune_cache_clear",
 ]
 
 _L = None
@@ -112,6 +112,7 @@ def lib():
             "spmv_run_timed": (st, [st, vp, vp, vp, vp, vp, vp]),
             "spmv_spmm_timed": (st, [vp, vp, i64, vp, i64, i32, vp, vp, vp]),
             "spmv_batch_run_timed": (st, [vp, vp, vp, vp, vp, vp]),
+            "spmv_autotune_cache_clear": (None, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

@@ -94,3 +94,27 @@ def test_autotune_picks_a_valid_configuration(torch, fmt):
         assert p["sell_C"] in (8, 16, 32, 64)
     if fmt == "csr5":
         assert p["csr5_sigma"] in (4, 8, 16, 32)
+
+
+def test_autotune_cache_by_structure(torch):
+    import time
+    A = synth.zipf_rows(30_000, 30_000, 2.0, 12, 2000, 8, 9)
+    x = device_vec(synth.vector(A.N, 2), 0)
+    y = torch.empty(A.M, dtype=torch.float64, device="cuda")
+    S.lib().spmv_autotune_cache_clear()
+    Ad = S.Matrix.from_host(A)
+    t0 = time.perf_counter()
+    p1, ms1 = Ad.autotune("sell", x, y, scrub_bytes=64 << 20, reps=5)
+    t_first = time.perf_counter() - t0
+    # same structure, other values: served from the cache, no timing
+    A2 = synth.HostCSR(A.M, A.N, A.ptr, A.col, -2.0 * A.val)
+    t0 = time.perf_counter()
+    p2, ms2 = S.Matrix.from_host(A2).autotune("sell", x, y, scrub_bytes=64 << 20, reps=5)
+    t_second = time.perf_counter() - t0
+    assert p2 == p1 and ms2 == ms1
+    assert t_second < t_first
+    # another structure is tuned afresh
+    B = synth.uniform_random(30_000, 30_000, 12.0, 3, 4)
+    p3, _ = S.Matrix.from_host(B).autotune("sell", x, y, scrub_bytes=64 << 20, reps=5)
+    assert p3["sell_C"] in (8, 16, 32, 64)
+    S.lib().spmv_autotune_cache_clear()
