@@ -81,6 +81,8 @@ typedef struct {
                                   instead of each XCD taking a contiguous range of rows */
 #define SPMV_FLAG_SELL_SLICES 8u /* SELL: always the persistent column-slice kernel (default: chunks at most
                                     32 wide use the one-pass narrow kernel) */
+#define SPMV_FLAG_CSR_BANDS 16u /* CSR: split the columns into 8 bands, one per XCD, so each XCD's L2 holds its
+                                   eighth of x; per-band partial sums are added by a second pass */
 
 typedef struct {
   int32_t fmt, dtype;
@@ -129,7 +131,9 @@ spmv_status_t spmv_to_csr(spmv_mat_t A, int32_t* ptr, int32_t* col, void* val, i
  * "ptr","col","val" (CSR; CSR5 keeps CSR's ptr); "ell_col","ell_val"
  * (ELL and HYB, column-major M x K); "sell_perm","sell_cs","sell_col",
  * "sell_val"; "coo_row","coo_col","coo_val" (HYB); "tile_ptr","bit_flag",
- * "y_off","seg_off","tile_col","tile_val","tail_col","tail_val" (CSR5).
+ * "y_off","seg_off","tile_col","tile_val","tail_col","tail_val" (CSR5);
+ * "band_ptr","band_col","band_val" (CSR built with SPMV_FLAG_CSR_BANDS:
+ * 8 row-pointer arrays of M+1, then the bands' entries band after band).
  * spmv_array_bytes reports the size; export fails with INVALID_ARG when
  * bytes is smaller.  Synchronises s. */
 spmv_status_t spmv_array_bytes(spmv_mat_t A, const char* name, size_t* bytes);

@@ -157,6 +157,10 @@ spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* 
         SPMV_HIP(hipMemcpyAsync(A->val, csr->val, (size_t)A->sv * A->nnz, hipMemcpyDeviceToDevice, st));
         SPMV_TRY(csr_build_blocks(A, st));
         A->bytes_fmt = bytes_min(A);
+        if (A->params.flags & SPMV_FLAG_CSR_BANDS) {
+          SPMV_TRY(csr_build_bands(A, st));
+          A->bytes_fmt += (int64_t)(A->nbands - 1) * 4 * (A->M + 1);  // one row pointer per band
+        }
         SPMV_HIP(hipStreamSynchronize(st));
         return SPMV_OK;
       }
@@ -216,6 +220,9 @@ static spmv_status_t lookup(spmv_mat_t A, const char* name, const void** p, size
     int64_t b;
   } tab[] = {
       {"ptr", A->fmt == SPMV_FMT_CSR || A->fmt == SPMV_FMT_CSR5, A->ptr, 4 * (M + 1)},
+      {"band_ptr", A->nbands > 0, A->bptr, 4 * (int64_t)A->nbands * (M + 1)},
+      {"band_col", A->nbands > 0, A->bcol, 4 * nnz},
+      {"band_val", A->nbands > 0, A->bval, sv * nnz},
       {"col", A->fmt == SPMV_FMT_CSR, A->col, 4 * nnz},
       {"val", A->fmt == SPMV_FMT_CSR, A->val, sv * nnz},
       {"ell_col", A->fmt == SPMV_FMT_ELL || A->fmt == SPMV_FMT_HYB, A->ecol, 4 * M * A->K},

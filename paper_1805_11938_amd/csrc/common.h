@@ -133,6 +133,18 @@ struct spmv_mat_s {
   int2* segs = nullptr;        // (row, first nonzero) per segment
   int4* longs = nullptr;       // (row, first segment, segment count) per long row
   double* seg_part = nullptr;  // segment partial sums (run scratch)
+  // CSR column bands (SPMV_FLAG_CSR_BANDS): band b holds the entries with
+  // col in [b*band_w, (b+1)*band_w) as a CSR of all M rows
+  int32_t nbands = 0;
+  int64_t band_w = 0;
+  int32_t* bptr = nullptr;        // nbands x (M+1), each relative to its band's first entry
+  int32_t* bcol = nullptr;        // nnz, band after band
+  void* bval = nullptr;
+  int32_t* bblk = nullptr;        // row blocks of every band, concatenated
+  double* bpart = nullptr;        // nbands x M partial sums (run scratch)
+  std::vector<int64_t> band_off;  // host: first entry of each band (nbands+1)
+  std::vector<int64_t> band_nblk; // host: row blocks per band
+  std::vector<int64_t> band_blk0; // host: first row block of each band in bblk
 
   // ELL, and the ELL part of HYB: column-major M x K, slot (i,k) at k*M + i
   int64_t K = 0;
@@ -211,6 +223,7 @@ spmv_status_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------- builders
 spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s);
+spmv_status_t csr_build_bands(spmv_mat_s* A, hipStream_t s);
 spmv_status_t convert_ell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
 spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
 spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);

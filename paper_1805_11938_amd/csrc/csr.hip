@@ -22,7 +22,7 @@ namespace spmv {
 constexpr int CSR_W = 2048;    // rows + nonzeros per row block
 constexpr int CSR_CAP = 2560;  // nonzeros a block can stage in LDS
 constexpr int CSR_IT = CSR_CAP / BS;
-constexpr int CSR_LONG = 4096; // rows at least this long are reduced by a whole block
+constexpr int CSR_LONG = 1024; // rows at least this long are reduced by a whole block
 constexpr int WU_ROWS = 512;   // rows + nonzeros per wave unit (see k_csr_waves)
 constexpr int LONG_ROW = 1024; // rows longer than this are cut into segments for several waves
 constexpr int SEG = 512;       // nonzeros per long-row segment
@@ -165,68 +165,91 @@ __device__ __forceinline__ int lanes_for(int64_t nz, int64_t rows) {
 
 constexpr int CSR_RCAP = 512;  // row pointers a block stages in LDS
 
+// Rows [r0, r1) whose entries [k0, k1) fit the LDS staging (k1 - k0 <=
+// CSR_CAP): all loads in flight, products in LDS, each row reduced by V lanes.
+template <typename T, typename TY>
+__device__ __forceinline__ void csr_rows_staged(int64_t r0, int64_t r1, int64_t k0, int64_t k1,
+                                                const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                const T* __restrict__ val, const T* __restrict__ x,
+                                                TY* __restrict__ y, double* prod, int32_t* sptr) {
+  const int t = threadIdx.x;
+  const int64_t E = k1 - k0, nr = r1 - r0;
+  const bool staged = nr <= CSR_RCAP;
+  if (staged)
+    for (int64_t i = t; i <= nr; i += BS) sptr[i] = ptr[r0 + i] - (int32_t)k0;
+  if (E > 0) {  // clamped, branch-free loads and gathers keep every request in flight
+    int32_t c[CSR_IT];
+    T v[CSR_IT], xv[CSR_IT];
+    const int32_t* cb = col + k0;  // block-uniform bases, 32-bit lane offsets
+    const T* vb = val + k0;
+#pragma unroll
+    for (int j = 0; j < CSR_IT; ++j) {
+      const uint32_t k = (uint32_t)(t + j * BS), kk = k < (uint32_t)E ? k : (uint32_t)E - 1;
+      c[j] = ldnt32(cb, kk);
+      v[j] = ldnt32(vb, kk);
+    }
+    issue_fence();
+#pragma unroll
+    for (int j = 0; j < CSR_IT; ++j) xv[j] = ld32(x, (uint32_t)c[j]);
+    issue_fence();
+#pragma unroll
+    for (int j = 0; j < CSR_IT; ++j) {
+      const int64_t k = t + j * BS;
+      if (k < E) prod[k] = (double)v[j] * (double)xv[j];
+    }
+  }
+  __syncthreads();
+  const int V = lanes_for(E, nr);
+  const int g = t / V, lane = t % V, ng = BS / V;
+  for (int64_t r = g; r < nr; r += ng) {
+    const int a = staged ? sptr[r] : ptr[r0 + r] - (int32_t)k0;
+    const int e = staged ? sptr[r + 1] : ptr[r0 + r + 1] - (int32_t)k0;
+    double s = 0.0;
+    for (int k = a + lane; k < e; k += V) s += prod[k];
+    s = group_sum_rt(s, V);
+    if (lane == 0) y[r0 + r] = (TY)s;
+  }
+  __syncthreads();  // prod / sptr may be reused by the caller's next block
+}
+
 // One row block (all threads of the workgroup call this with the same rows).
-template <typename T>
+// TY is the type y is written in (T, or double for partial sums).  A block
+// whose entries overflow the LDS staging ends in a long row (the split puts
+// at most W rows-plus-nonzeros before it): the rows before that overflow go
+// through the staged path, the rest are summed from global memory -- a wave
+// per row below CSR_LONG, the whole block above.
+template <typename T, typename TY = T>
 __device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, int64_t k0, int64_t k1,
                                                const int32_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col, const T* __restrict__ val,
-                                               const T* __restrict__ x, T* __restrict__ y, double* prod,
+                                               const T* __restrict__ x, TY* __restrict__ y, double* prod,
                                                int32_t* sptr) {
   if (r0 >= r1) return;
-  const int t = threadIdx.x;
-  const int64_t E = k1 - k0, nr = r1 - r0;
-  if (E <= CSR_CAP) {
-    const bool staged = nr <= CSR_RCAP;
-    if (staged)
-      for (int64_t i = t; i <= nr; i += BS) sptr[i] = ptr[r0 + i] - (int32_t)k0;
-    if (E > 0) {  // clamped, branch-free loads and gathers keep every request in flight
-      int32_t c[CSR_IT];
-      T v[CSR_IT], xv[CSR_IT];
-      const int32_t* cb = col + k0;  // block-uniform bases, 32-bit lane offsets
-      const T* vb = val + k0;
-#pragma unroll
-      for (int j = 0; j < CSR_IT; ++j) {
-        const uint32_t k = (uint32_t)(t + j * BS), kk = k < (uint32_t)E ? k : (uint32_t)E - 1;
-        c[j] = ldnt32(cb, kk);
-        v[j] = ldnt32(vb, kk);
-      }
-      issue_fence();
-#pragma unroll
-      for (int j = 0; j < CSR_IT; ++j) xv[j] = ld32(x, (uint32_t)c[j]);
-      issue_fence();
-#pragma unroll
-      for (int j = 0; j < CSR_IT; ++j) {
-        const int64_t k = t + j * BS;
-        if (k < E) prod[k] = (double)v[j] * (double)xv[j];
-      }
-    }
-    __syncthreads();
-    const int V = lanes_for(E, nr);
-    const int g = t / V, lane = t % V, ng = BS / V;
-    for (int64_t r = g; r < nr; r += ng) {
-      const int a = staged ? sptr[r] : ptr[r0 + r] - (int32_t)k0;
-      const int e = staged ? sptr[r + 1] : ptr[r0 + r + 1] - (int32_t)k0;
-      double s = 0.0;
-      for (int k = a + lane; k < e; k += V) s += prod[k];
-      s = group_sum_rt(s, V);
-      if (lane == 0) y[r0 + r] = (T)s;
-    }
-    __syncthreads();  // prod / sptr may be reused by the caller's next block
+  if (k1 - k0 <= CSR_CAP) {
+    csr_rows_staged<T, TY>(r0, r1, k0, k1, ptr, col, val, x, y, prod, sptr);
     return;
   }
-  // long path: a wave per row below CSR_LONG, the whole block above
+  int64_t lo = r0 + 1, hi = r1;  // first r with ptr[r] - k0 > CSR_CAP (ptr[r1] qualifies)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (ptr[mid] - k0 > CSR_CAP) hi = mid;
+    else lo = mid + 1;
+  }
+  const int64_t rl = lo - 1;  // rows [r0, rl) fit the staging
+  if (rl > r0) csr_rows_staged<T, TY>(r0, rl, k0, ptr[rl], ptr, col, val, x, y, prod, sptr);
+  const int t = threadIdx.x;
   const int w = t / WAVE, lane = __lane_id();
-  for (int64_t r = r0 + w; r < r1; r += BS / WAVE) {
+  for (int64_t r = rl + w; r < r1; r += BS / WAVE) {
     const int64_t a = ptr[r], e = ptr[r + 1];
     if (e - a >= CSR_LONG) continue;
     double s = group_sum<64>(row_dot(col, val, x, a, e, lane, WAVE));
-    if (lane == 0) y[r] = (T)s;
+    if (lane == 0) y[r] = (TY)s;
   }
-  for (int64_t r = r0; r < r1; ++r) {
+  for (int64_t r = rl; r < r1; ++r) {
     const int64_t a = ptr[r], e = ptr[r + 1];
     if (e - a < CSR_LONG) continue;
     const double s = block_sum(row_dot(col, val, x, a, e, t, BS), prod);
-    if (t == 0) y[r] = (T)s;
+    if (t == 0) y[r] = (TY)s;
   }
   __syncthreads();
 }
@@ -243,6 +266,154 @@ __global__ __launch_bounds__(BS) void k_csr_rows(int64_t nblk, const int32_t* __
   csr_rows_block<T>(r0, r1, ptr[r0], ptr[r1], ptr, col, val, x, y, prod, sptr);
 }
 
+// ------------------------------------------------------- column bands
+// The columns are split into NBANDS equal bands and each band is stored as a
+// CSR of all M rows.  Workgroup g works on band g mod 8 -- the XCD the
+// hardware dispatches it to -- so each XCD's L2 caches only its eighth of x,
+// which matters when x is larger than one L2 and the columns are scattered.
+// Every row of every band is written (0 for a row with no entries there) to
+// an FP64 partial-sum vector; k_csr_band_sum adds the bands in order.
+constexpr int NBANDS = 8;
+
+struct BandSet {
+  const int32_t* ptr[NBANDS];
+  const int32_t* col[NBANDS];
+  const void* val[NBANDS];
+  const int32_t* blk[NBANDS];
+  int64_t nblk[NBANDS];
+};
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_bands(BandSet b, int64_t M, const T* __restrict__ x,
+                                                  double* __restrict__ part) {
+  __shared__ double prod[CSR_CAP];
+  __shared__ int32_t sptr[CSR_RCAP + 1];
+  const int band = blockIdx.x % NBANDS;
+  const int64_t j = blockIdx.x / NBANDS;
+  if (j >= b.nblk[band]) return;
+  const int32_t* ptr = b.ptr[band];
+  const int64_t r0 = b.blk[band][j], r1 = b.blk[band][j + 1];
+  csr_rows_block<T, double>(r0, r1, ptr[r0], ptr[r1], ptr, b.col[band], (const T*)b.val[band], x,
+                            part + band * M, prod, sptr);
+}
+
+template <typename T>
+__global__ void k_csr_band_sum(int64_t M, const double* __restrict__ part, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < NBANDS; ++b) s += part[b * M + i];
+    y[i] = (T)s;
+  }
+}
+
+// entries of each row in each band (columns are sorted: binary searches)
+__global__ void k_band_count(int64_t M, const int32_t* ptr, const int32_t* col, int64_t bw, int32_t* cnt) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ptr[r], e = ptr[r + 1];
+    int64_t prev = a;
+    for (int b = 0; b < NBANDS; ++b) {
+      int64_t lo = prev, hi = e;  // first entry with col >= (b+1)*bw
+      const int64_t lim = (b + 1) * bw;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < lim) lo = mid + 1;
+        else hi = mid;
+      }
+      cnt[b * M + r] = (int32_t)(lo - prev);
+      prev = lo;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_band_scatter(int64_t M, const int32_t* ptr, const int32_t* col, const T* val, const int32_t* cnt,
+                               const int32_t* bptr, const int64_t* boff, int32_t* bcol, T* bval) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = ptr[r];
+    for (int b = 0; b < NBANDS; ++b) {
+      const int64_t dst = boff[b] + bptr[b * (M + 1) + r];
+      const int32_t n = cnt[b * M + r];
+      for (int32_t q = 0; q < n; ++q) {
+        bcol[dst + q] = col[k + q];
+        bval[dst + q] = val[k + q];
+      }
+      k += n;
+    }
+  }
+}
+
+spmv_status_t csr_build_bands(spmv_mat_s* A, hipStream_t s) {
+  const int64_t M = A->M;
+  A->nbands = NBANDS;
+  A->band_w = std::max<int64_t>(1, cdiv(A->N, NBANDS));
+  DTmp cnt, doff;
+  SPMV_TRY(cnt.alloc(sizeof(int32_t) * NBANDS * std::max<int64_t>(M, 1)));
+  SPMV_TRY(mat_alloc(A, (void**)&A->bptr, sizeof(int32_t) * NBANDS * (M + 1)));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M, BS), 65536));
+  if (M) {
+    k_band_count<<<g, BS, 0, s>>>(M, A->ptr, A->col, A->band_w, cnt.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+  }
+  A->band_off.assign(NBANDS + 1, 0);
+  for (int b = 0; b < NBANDS; ++b) {
+    SPMV_TRY(scan_i32_to_i32(cnt.as<int32_t>() + b * M, A->bptr + b * (M + 1), M, s));
+    int32_t nb = 0;
+    SPMV_TRY(copy_to_host(&nb, A->bptr + b * (M + 1) + M, sizeof(int32_t), s));
+    A->band_off[b + 1] = A->band_off[b] + nb;
+  }
+  SPMV_TRY(mat_alloc(A, (void**)&A->bcol, sizeof(int32_t) * A->nnz));
+  SPMV_TRY(mat_alloc(A, &A->bval, (size_t)A->sv * A->nnz));
+  SPMV_TRY(doff.alloc(sizeof(int64_t) * (NBANDS + 1)));
+  SPMV_HIP(hipMemcpyAsync(doff.p, A->band_off.data(), sizeof(int64_t) * (NBANDS + 1), hipMemcpyHostToDevice, s));
+  if (M) {
+    if (A->dt == SPMV_F64)
+      k_band_scatter<double><<<g, BS, 0, s>>>(M, A->ptr, A->col, (const double*)A->val, cnt.as<int32_t>(), A->bptr,
+                                              doff.as<int64_t>(), A->bcol, (double*)A->bval);
+    else
+      k_band_scatter<float><<<g, BS, 0, s>>>(M, A->ptr, A->col, (const float*)A->val, cnt.as<int32_t>(), A->bptr,
+                                             doff.as<int64_t>(), A->bcol, (float*)A->bval);
+    SPMV_LAUNCH_CHECK();
+  }
+  // row blocks of each band (the same merged rows + nonzeros split)
+  A->band_nblk.assign(NBANDS, 0);
+  A->band_blk0.assign(NBANDS + 1, 0);
+  for (int b = 0; b < NBANDS; ++b) {
+    A->band_nblk[b] = std::max<int64_t>(1, cdiv(M + (A->band_off[b + 1] - A->band_off[b]), CSR_W));
+    A->band_blk0[b + 1] = A->band_blk0[b] + A->band_nblk[b] + 1;
+  }
+  SPMV_TRY(mat_alloc(A, (void**)&A->bblk, sizeof(int32_t) * A->band_blk0[NBANDS]));
+  for (int b = 0; b < NBANDS; ++b) {
+    const int64_t n = A->band_nblk[b];
+    k_csr_blocks<<<(unsigned)std::min<int64_t>(cdiv(n + 1, BS), 65536), BS, 0, s>>>(A->bptr + b * (M + 1), M, n,
+                                                                                   CSR_W, A->bblk + A->band_blk0[b]);
+    SPMV_LAUNCH_CHECK();
+  }
+  SPMV_TRY(mat_alloc(A, (void**)&A->bpart, sizeof(double) * NBANDS * std::max<int64_t>(M, 1)));
+  SPMV_HIP(hipStreamSynchronize(s));
+  return SPMV_OK;
+}
+
+template <typename T>
+static spmv_status_t run_csr_bands(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
+  BandSet b;
+  int64_t maxb = 0;
+  for (int i = 0; i < NBANDS; ++i) {
+    b.ptr[i] = A->bptr + i * (A->M + 1);
+    b.col[i] = A->bcol + A->band_off[i];
+    b.val[i] = (const char*)A->bval + (size_t)A->sv * A->band_off[i];
+    b.blk[i] = A->bblk + A->band_blk0[i];
+    b.nblk[i] = A->band_nblk[i];
+    maxb = std::max(maxb, A->band_nblk[i]);
+  }
+  launch(k_csr_bands<T>, (unsigned)(maxb * NBANDS), BS, s, b, A->M, x, A->bpart);
+  SPMV_LAUNCH_CHECK();
+  launch(k_csr_band_sum<T>, (unsigned)std::min<int64_t>(cdiv(A->M, BS), 65536), BS, s, A->M,
+         (const double*)A->bpart, y);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
+}
+
 // ------------------------------------------------------------ wave units
 // Default CSR kernel: the same merged (rows + nonzeros) split, in units of
 // WU for one wave each.  Waves never wait on each other (no workgroup
@@ -253,7 +424,7 @@ __global__ __launch_bounds__(BS) void k_csr_rows(int64_t nblk, const int32_t* __
 constexpr int WU = WU_ROWS;         // rows + nonzeros per wave unit
 constexpr int WCAP = 512;           // products a wave stages in LDS
 constexpr int WIT = WCAP / WAVE;
-constexpr int WRCAP = 128;          // row pointers a wave stages in LDS
+constexpr int WRCAP = WU;           // row pointers a wave stages in LDS (a unit never has more rows)
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -386,6 +557,7 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   const int V = A->params.csr_lanes_per_row;
   const int32_t* ptr = A->ptr;
   const T* val = (const T*)A->val;
+  if (V == 0 && A->nbands > 0) return run_csr_bands<T>(A, x, y, s);
   if (V == 0) {
     if (!(A->params.flags & SPMV_FLAG_CSR_WAVES)) {
       if (A->params.flags & SPMV_FLAG_LINEAR)
@@ -643,7 +815,7 @@ __global__ void k_coo_heads(const uint64_t* key, int64_t n, int32_t* head) {
 
 template <typename T>
 __global__ void k_coo_reduce(const uint64_t* key, const uint32_t* idx, const T* vin, int64_t n, int64_t N,
-                             const int32_t* pos, int32_t* col, T* vout, int32_t* rowcnt) {
+                             const int32_t* pos, int32_t* col, T* vout, int32_t* urow) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     if (!(i == 0 || key[i] != key[i - 1])) continue;
     double s = (double)vin[idx[i]];
@@ -652,7 +824,22 @@ __global__ void k_coo_reduce(const uint64_t* key, const uint32_t* idx, const T* 
     const int32_t u = pos[i];
     col[u] = (int32_t)(key[i] % (uint64_t)N);
     vout[u] = (T)s;
-    atomicAdd(&rowcnt[key[i] / (uint64_t)N], 1);
+    urow[u] = (int32_t)(key[i] / (uint64_t)N);
+  }
+}
+
+// ptr[r] = number of unique entries in rows before r: a lower bound in the
+// (sorted) row of each unique entry; no atomics, so long rows cost nothing
+// extra.
+__global__ void k_coo_ptr(int64_t M, int64_t U, const int32_t* urow, int32_t* ptr) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= M; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = U;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (urow[mid] < r) lo = mid + 1;
+      else hi = mid;
+    }
+    ptr[r] = (int32_t)lo;
   }
 }
 
@@ -717,22 +904,23 @@ spmv_status_t mat_from_coo(int64_t M, int64_t N, int64_t n, const int32_t* row, 
   int32_t U = 0;
   SPMV_TRY(copy_to_host(&U, pos.as<int32_t>() + n, sizeof(int32_t), s));
   A->nnz = U;
-  DTmp rowcnt;
-  SPMV_TRY(rowcnt.alloc(sizeof(int32_t) * (M + 1)));
-  SPMV_HIP(hipMemsetAsync(rowcnt.p, 0, sizeof(int32_t) * (M + 1), s));
+  DTmp urow;
+  SPMV_TRY(urow.alloc(sizeof(int32_t) * std::max<int64_t>(U, 1)));
   SPMV_TRY(mat_alloc(A, (void**)&A->ptr, sizeof(int32_t) * (M + 1)));
   SPMV_TRY(mat_alloc(A, (void**)&A->col, sizeof(int32_t) * U));
   SPMV_TRY(mat_alloc(A, &A->val, (size_t)sv * U));
   if (n) {
     if (dt == SPMV_F64)
       k_coo_reduce<double><<<g, BS, 0, s>>>(keys, idx, (const double*)val_in, n, N, pos.as<int32_t>(), A->col,
-                                            (double*)A->val, rowcnt.as<int32_t>());
+                                            (double*)A->val, urow.as<int32_t>());
     else
       k_coo_reduce<float><<<g, BS, 0, s>>>(keys, idx, (const float*)val_in, n, N, pos.as<int32_t>(), A->col,
-                                           (float*)A->val, rowcnt.as<int32_t>());
+                                           (float*)A->val, urow.as<int32_t>());
     SPMV_LAUNCH_CHECK();
   }
-  SPMV_TRY(scan_i32_to_i32(rowcnt.as<int32_t>(), A->ptr, M, s));
+  k_coo_ptr<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M + 1, BS), 65536)), BS, 0, s>>>(
+      M, U, urow.as<int32_t>(), A->ptr);
+  SPMV_LAUNCH_CHECK();
   SPMV_TRY(csr_build_blocks(A, s));
   A->bytes_fmt = bytes_min(A);
   SPMV_HIP(hipStreamSynchronize(s));

@@ -331,24 +331,34 @@ __global__ void k_sell_width(int64_t M, int64_t nch, int C, const int32_t* ptr, 
 }
 
 template <typename T>
-__global__ void k_csr_to_sell(int64_t M, int64_t Mpad, int C, const int32_t* ptr, const int32_t* col, const T* val,
-                              const int32_t* perm, const int64_t* cs, int32_t* scol, T* sval) {
-  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < Mpad;
-       pos += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = pos / C, p = pos % C;
-    const int64_t r = perm ? perm[pos] : (pos < M ? pos : -1);
-    const int64_t a = r >= 0 ? ptr[r] : 0, len = r >= 0 ? ptr[r + 1] - a : 0;
-    const int64_t base = cs[c], w = (cs[c + 1] - base) / C;
-    for (int64_t k = 0; k < w; ++k) {
-      const int64_t q = base + k * C + p;
-      if (k < len) {
-        scol[q] = col[a + k];
-        sval[q] = val[a + k];
+__global__ __launch_bounds__(WAVE) void k_csr_to_sell(int64_t M, int64_t nchunks, int C, const int32_t* ptr,
+                                                      const int32_t* col, const T* val, const int32_t* perm,
+                                                      const int64_t* cs, int32_t* scol, T* sval) {
+  // one wave per chunk: the chunk's rows are looked up once, then its C x w
+  // slots are written slot-major (coalesced) by all lanes together, so a
+  // chunk holding one very long row is filled in parallel
+  __shared__ int64_t ra[WAVE], rl[WAVE];
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int t = threadIdx.x;
+    if (t < C) {
+      const int64_t pos = c * C + t;
+      const int64_t r = perm ? perm[pos] : (pos < M ? pos : -1);
+      ra[t] = r >= 0 ? ptr[r] : 0;
+      rl[t] = r >= 0 ? ptr[r + 1] - ra[t] : 0;
+    }
+    __syncthreads();
+    const int64_t base = cs[c], n = cs[c + 1] - base;
+    for (int64_t q = t; q < n; q += WAVE) {
+      const int64_t k = q / C, p = q % C;
+      if (k < rl[p]) {
+        scol[base + q] = col[ra[p] + k];
+        sval[base + q] = val[ra[p] + k];
       } else {
-        scol[q] = -1;
-        sval[q] = (T)0;
+        scol[base + q] = -1;
+        sval[base + q] = (T)0;
       }
     }
+    __syncthreads();
   }
 }
 
@@ -655,12 +665,13 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   SPMV_TRY(mat_alloc(A, (void**)&A->scol, sizeof(int32_t) * A->nslots));
   SPMV_TRY(mat_alloc(A, &A->sval, (size_t)A->sv * A->nslots));
   if (A->Mpad) {
+    const unsigned gc = (unsigned)std::min<int64_t>(A->nchunks, (int64_t)1 << 20);
     if (A->dt == SPMV_F64)
-      k_csr_to_sell<double><<<g, BS, 0, s>>>(M, A->Mpad, C, src->ptr, src->col, (const double*)src->val, A->perm, A->cs,
-                                             A->scol, (double*)A->sval);
+      k_csr_to_sell<double><<<gc, WAVE, 0, s>>>(M, A->nchunks, C, src->ptr, src->col, (const double*)src->val,
+                                                A->perm, A->cs, A->scol, (double*)A->sval);
     else
-      k_csr_to_sell<float><<<g, BS, 0, s>>>(M, A->Mpad, C, src->ptr, src->col, (const float*)src->val, A->perm, A->cs,
-                                            A->scol, (float*)A->sval);
+      k_csr_to_sell<float><<<gc, WAVE, 0, s>>>(M, A->nchunks, C, src->ptr, src->col, (const float*)src->val,
+                                               A->perm, A->cs, A->scol, (float*)A->sval);
     SPMV_LAUNCH_CHECK();
   }
   // work items: column slices of at most SELL_KT per chunk

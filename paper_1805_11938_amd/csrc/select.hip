@@ -278,8 +278,12 @@ spmv_status_t features(spmv_mat_s* A, double* out_host, hipStream_t s) {
     SPMV_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * nv, s));
     k_feat_hist<<<(unsigned)std::min<int64_t>(g, 512), BS, 0, s>>>(M, nv, A->ptr, hist);
     SPMV_LAUNCH_CHECK();
-    k_feat_below<<<1, BS, 0, s>>>(nv, hist, below);
-    SPMV_LAUNCH_CHECK();
+    if (nv <= 65536) {  // short: one workgroup, no temporaries
+      k_feat_below<<<1, BS, 0, s>>>(nv, hist, below);
+      SPMV_LAUNCH_CHECK();
+    } else {
+      SPMV_TRY(scan_i32_to_i64(hist, below, nv, s));
+    }
     const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(nv, BS), 2048));
     k_feat_gini<<<gv, BS, 0, s>>>(nv, M, hist, below, acc);
     SPMV_LAUNCH_CHECK();

@@ -42,6 +42,7 @@ FORMAT_CONFIGS = [
     ("csr", {"csr_lanes_per_row": 64}),
     ("csr", {"flags": 2}),
     ("csr", {"flags": 4}),
+    ("csr", {"flags": 16}),
     ("csr5", {}),
     ("csr5", {"csr5_sigma": 4}),
     ("csr5", {"csr5_sigma": 32}),

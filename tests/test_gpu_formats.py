@@ -255,3 +255,29 @@ def test_timing_protocol(torch):
     y = torch.empty(A.M, dtype=torch.float64, device="cuda")
     r = A.time(x, y, warmup=2, min_reps=20, max_reps=200, scrub_bytes=64 << 20)
     assert r["reps"] >= 20 and 0 < r["min_ms"] <= r["median_ms"] < 10
+
+
+def test_csr_bands_structure(torch):
+    """CSR with column bands: band b holds, row by row, the entries whose
+    column lies in [b*w, (b+1)*w) with w = ceil(N/8), values bit for bit."""
+    A = synth.random_pattern(700, 1000, 0.03, 21)
+    B = S.Matrix.from_host(A).convert("csr", flags=16)
+    bp = B.export("band_ptr", np.int32).reshape(8, A.M + 1)
+    bc = B.export("band_col", np.int32)
+    bv = B.export("band_val", np.float64)
+    w = -(-A.N // 8)
+    off = 0
+    for b in range(8):
+        rows_c, rows_v = [], []
+        for i in range(A.M):
+            c = A.col[A.ptr[i]:A.ptr[i + 1]]
+            v = A.val[A.ptr[i]:A.ptr[i + 1]]
+            m = (c >= b * w) & (c < (b + 1) * w)
+            assert bp[b, i + 1] - bp[b, i] == m.sum()
+            rows_c.append(c[m])
+            rows_v.append(v[m])
+        n = bp[b, -1]
+        assert np.array_equal(bc[off:off + n], np.concatenate(rows_c))
+        assert np.array_equal(bv[off:off + n].view(np.uint64), np.concatenate(rows_v).view(np.uint64))
+        off += n
+    assert off == A.nnz
