@@ -615,9 +615,11 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
   const int t = threadIdx.x;
   const int G = BS / k;
   const int g = t / k, c = t % k;
-  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+  {  // one workgroup per row block, each XCD a contiguous range of blocks
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= nblk) return;
     const int64_t r0 = blk_row[b], r1 = blk_row[b + 1];
-    if (r0 >= r1) continue;
+    if (r0 >= r1) return;
     const int64_t k0 = ptr[r0], E = ptr[r1] - k0;
     if (E <= SPMM_CAP) {
       if (E > 0) {  // all staging loads in flight (clamped, branch-free), then the LDS stores
@@ -644,22 +646,22 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
         for (int64_t r = r0 + g; r < r1; r += G) {
           const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
           double s4[4] = {0.0, 0.0, 0.0, 0.0};
-          // 8 nonzeros at a time, all 8 gathers of X rows in flight; the
+          // 16 nonzeros at a time, all 16 gathers of X rows in flight; the
           // last group repeats entry e-1 for its unused places and masks them
-          for (int q = a; q < e; q += 8) {
-            const int n = e - q < 8 ? e - q : 8;
-            int32_t cq[8];
-            T vq[8], xq[8];
+          for (int q = a; q < e; q += 16) {
+            const int n = e - q < 16 ? e - q : 16;
+            int32_t cq[16];
+            T vq[16], xq[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
               const int qq = q + (u < n ? u : n - 1);
               cq[u] = scol[qq];
               vq[u] = sval[qq];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xq[u] = X[(int64_t)cq[u] * ldx + c];
+            for (int u = 0; u < 16; ++u) xq[u] = X[(int64_t)cq[u] * ldx + c];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s4[u & 3] += u < n ? (double)vq[u] * (double)xq[u] : 0.0;
+            for (int u = 0; u < 16; ++u) s4[u & 3] += u < n ? (double)vq[u] * (double)xq[u] : 0.0;
           }
           Y[r * ldy + c] = (T)((s4[0] + s4[1]) + (s4[2] + s4[3]));
         }
@@ -689,7 +691,7 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
   if (A->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_UNSUPPORTED, "spmm runs on CSR handles");
   if (k < 1 || k > 64 || ldx < k || ldy < k) return fail(SPMV_ERR_INVALID_ARG, "spmm needs 1 <= k <= 64, ld >= k");
   if (A->M == 0) return SPMV_OK;
-  const unsigned g = (unsigned)std::min<int64_t>(A->nblk, resident_blocks(4));
+  const unsigned g = (unsigned)A->nblk;  // one workgroup per row block
   if (A->dt == SPMV_F64)
     launch(k_csr_spmm<double>, g, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const double*)A->val,
                                         (const double*)X, ldx, (double*)Y, ldy, k);

@@ -281,3 +281,33 @@ def test_csr_bands_structure(torch):
         assert np.array_equal(bv[off:off + n].view(np.uint64), np.concatenate(rows_v).view(np.uint64))
         off += n
     assert off == A.nnz
+
+
+def test_matrix_market_file_through_the_device(torch, tmp_path):
+    """A Matrix Market file (written here, with duplicates and a symmetric
+    header) read, canonicalised on the device, converted and run."""
+    from paper_1805_11938_amd import mmio
+    rng = np.random.default_rng(8)
+    n = 300
+    r = rng.integers(0, n, 3000)
+    c = rng.integers(0, n, 3000)
+    lo = np.minimum(r, c)
+    hi = np.maximum(r, c)  # lower triangle for the symmetric file
+    p = str(tmp_path / "s.mtx")
+    with open(p, "w") as f:
+        f.write("%%MatrixMarket matrix coordinate real symmetric\n")
+        f.write(f"{n} {n} {len(r)}\n")
+        for a, b, v in zip(hi, lo, rng.standard_normal(len(r))):
+            f.write(f"{a + 1} {b + 1} {v!r}\n")
+    C = mmio.read(p)
+    ptr, col, val = oracle.coo_to_csr(C.M, C.N, C.row, C.col, C.val)
+    Ad = S.Matrix.from_coo(C.M, C.N, C.row, C.col, C.val)
+    dp, dc, dv = Ad.to_csr()
+    assert np.array_equal(dp, ptr) and np.array_equal(dc, col) and np.array_equal(dv.view(np.uint64), val.view(np.uint64))
+    H = synth.HostCSR(C.M, C.N, ptr, col, val)
+    x64 = synth.vector(n, 3)
+    yref, den = reference(H, x64, 0)
+    x = device_vec(x64, 0)
+    for fmt, kw in FORMAT_CONFIGS:
+        out = Ad.convert(fmt, **kw).run(x).cpu().numpy()
+        assert rowwise_err(out, yref, den) <= TOL[0], (fmt, kw)
