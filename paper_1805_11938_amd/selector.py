@@ -302,6 +302,35 @@ def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB):
     return Ad.convert(fmt, **(params or {})), fmt, "exhaustive"
 
 
+def worth_converting(t_convert_ms, t_csr_ms, t_fmt_ms, calls):
+    """Conversion-aware choice: converting pays off when the time saved over
+    `calls` SpMVs exceeds the one-off conversion (the paper measures SpMV
+    alone and notes that conversion costs a few SpMVs)."""
+    return calls * (t_csr_ms - t_fmt_ms) > t_convert_ms
+
+
+def auto_for_calls(Ad, x, y, model, calls, scrub=SCRUB):
+    """The model's format, kept only if its conversion is repaid within
+    `calls` SpMVs: the conversion is timed, then one cold launch of each of
+    CSR and the converted handle.  Returns (handle, format, detail)."""
+    import torch
+    fmt, _ = choose(Ad, model)
+    if fmt == "csr":
+        return Ad, "csr", {"reason": "model chose csr"}
+    e0, e1 = S.timing_events()
+    e0.record()
+    B = Ad.convert(fmt)
+    e1.record()
+    torch.cuda.synchronize()
+    t_conv = e0.elapsed_time(e1)
+    t_csr = Ad.time(x, y, warmup=1, min_reps=5, max_reps=20, scrub_bytes=scrub)["median_ms"]
+    t_fmt = B.time(x, y, warmup=1, min_reps=5, max_reps=20, scrub_bytes=scrub)["median_ms"]
+    detail = {"t_convert_ms": t_conv, "t_csr_ms": t_csr, "t_fmt_ms": t_fmt, "calls": calls}
+    if worth_converting(t_conv, t_csr, t_fmt, calls):
+        return B, fmt, detail
+    return Ad, "csr", detail
+
+
 def host_scale(F, lo=None, hi=None):
     """The feature transform and min-max scaling of spmv_scale_features,
     on the host, for the CPU classifiers below (returns X, lo, hi)."""

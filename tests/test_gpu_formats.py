@@ -298,7 +298,7 @@ def test_matrix_market_file_through_the_device(torch, tmp_path):
         f.write("%%MatrixMarket matrix coordinate real symmetric\n")
         f.write(f"{n} {n} {len(r)}\n")
         for a, b, v in zip(hi, lo, rng.standard_normal(len(r))):
-            f.write(f"{a + 1} {b + 1} {v!r}\n")
+            f.write(f"{a + 1} {b + 1} {float(v)!r}\n")
     C = mmio.read(p)
     ptr, col, val = oracle.coo_to_csr(C.M, C.N, C.row, C.col, C.val)
     Ad = S.Matrix.from_coo(C.M, C.N, C.row, C.col, C.val)

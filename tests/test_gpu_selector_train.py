@@ -129,3 +129,22 @@ def test_auto_uses_model_or_exhaustive_fallback(torch, trained):
     assert rowwise_err(B2.run(x).cpu().numpy(), yref, den) <= TOL[0]
     B3, _, how3 = SEL.auto(Ad, x, y, None, scrub=64 << 20)
     assert how3 == "exhaustive"
+
+
+def test_auto_for_calls_keeps_csr_for_few_calls(torch, trained):
+    (models, _) = trained
+    model, _ = models["f64"]
+    A = synth.zipf_rows(200_000, 200_000, 2.0, 16, 8_000, 31, 32)
+    Ad = SEL._to_device(A, S.F64)
+    x = device_vec(synth.vector(A.N, 33), 0)
+    y = torch.empty(A.M, dtype=torch.float64, device="cuda")
+    fmt, _ = SEL.choose(Ad, model)
+    B1, f1, d1 = SEL.auto_for_calls(Ad, x, y, model, calls=1, scrub=64 << 20)
+    Bn, fn, dn = SEL.auto_for_calls(Ad, x, y, model, calls=10**6, scrub=64 << 20)
+    if fmt != "csr":
+        for f, d, calls in ((f1, d1, 1), (fn, dn, 10**6)):
+            pays = SEL.worth_converting(d["t_convert_ms"], d["t_csr_ms"], d["t_fmt_ms"], calls)
+            assert f == (fmt if pays else "csr")
+        assert d1["t_convert_ms"] > 0
+    yref, den = reference(A, synth.vector(A.N, 33), 0)
+    assert rowwise_err(Bn.run(x).cpu().numpy(), yref, den) <= TOL[0]

@@ -102,3 +102,10 @@ def test_paper_classifiers_on_the_profiled_table():
     assert r["dtc"]["frac"] >= 0.95
     for name in ("dtc", "knn1", "lr", "rfc", "vote"):
         assert r[name]["frac"] > r["fixed_csr"]["frac"], name
+
+
+def test_conversion_pays_off_rule():
+    # 10 ms to convert, 1 ms saved per call: worth it from 11 calls on
+    assert not SEL.worth_converting(10.0, 3.0, 2.0, 10)
+    assert SEL.worth_converting(10.0, 3.0, 2.0, 11)
+    assert not SEL.worth_converting(0.0, 2.0, 3.0, 1000)  # a slower format never pays
