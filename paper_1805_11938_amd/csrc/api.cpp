@@ -1,5 +1,6 @@
 // C-ABI of libspmv: argument checking, handle lifetime, format dispatch and
 // array export.  All arithmetic happens in the kernels of the .hip files.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -31,6 +32,7 @@ void resolve_params(const spmv_params_t* in, spmv_params_t* out) {
   d.csr5_sigma = 16;
   d.max_bytes = 0;
   d.flags = 0;
+  d.bands = 1;
   if (in) {
     if (in->sell_C > 0) d.sell_C = in->sell_C;
     if (in->sell_sigma > 0) d.sell_sigma = in->sell_sigma;
@@ -40,6 +42,7 @@ void resolve_params(const spmv_params_t* in, spmv_params_t* out) {
     if (in->csr5_sigma > 0) d.csr5_sigma = in->csr5_sigma;
     if (in->max_bytes > 0) d.max_bytes = in->max_bytes;
     d.flags = in->flags;
+    if (in->bands > 0) d.bands = in->bands;
   }
   *out = d;
 }
@@ -52,6 +55,7 @@ spmv_status_t dispatch_run(spmv_mat_s* A, const void* x, void* y, hipStream_t s)
   // the kernels address x, and ELL/SELL columns, with 32-bit byte offsets
   if (A->N * A->sv >= ((int64_t)1 << 32) || A->M * A->sv >= ((int64_t)1 << 32))
     return fail(SPMV_ERR_UNSUPPORTED, "x or y larger than 4 GiB");
+  if (!A->sub.empty()) return run_banded(A, x, y, s);
   switch (A->fmt) {
     case SPMV_FMT_CSR: return run_csr(A, x, y, s);
     case SPMV_FMT_CSR5: return run_csr5(A, x, y, s);
@@ -145,6 +149,7 @@ spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* 
     A->nnz = csr->nnz;
     A->sv = csr->sv;
     resolve_params(p, &A->params);
+    if (A->params.bands > 1) return convert_banded(csr, A, st);
     switch (fmt) {
       case SPMV_FMT_CSR: {
         const int V = A->params.csr_lanes_per_row;
@@ -187,7 +192,9 @@ spmv_status_t spmv_to_csr(spmv_mat_t A, int32_t* ptr, int32_t* col, void* val, i
     dc = tc.as<int32_t>();
     dv = tv.p;
   }
-  switch (A->fmt) {
+  if (!A->sub.empty()) {
+    SPMV_TRY(banded_to_csr(A, dp, dc, dv, st));
+  } else switch (A->fmt) {
     case SPMV_FMT_CSR:
       SPMV_HIP(hipMemcpyAsync(dp, A->ptr, sizeof(int32_t) * (A->M + 1), hipMemcpyDeviceToDevice, st));
       if (A->nnz) {
@@ -211,6 +218,15 @@ spmv_status_t spmv_to_csr(spmv_mat_t A, int32_t* ptr, int32_t* col, void* val, i
 
 static spmv_status_t lookup(spmv_mat_t A, const char* name, const void** p, size_t* bytes) {
   if (!A || !name) return fail(SPMV_ERR_INVALID_ARG, "null argument");
+  if (!strncmp(name, "band", 4) && name[4] >= '0' && name[4] <= '9') {  // "band<b>.<array>" of a banded SELL
+    char* rest = nullptr;
+    const long b = strtol(name + 4, &rest, 10);
+    if (*rest != '.' || b < 0 || b >= (long)A->sub.size())
+      return fail(SPMV_ERR_INVALID_ARG, "array '%s' does not exist for this handle", name);
+    return lookup(A->sub[b].get(), rest + 1, p, bytes);
+  }
+  const bool own = A->sub.empty();  // a banded handle keeps its arrays in its bands
+  const bool sell = A->fmt == SPMV_FMT_SELL && own;
   const int64_t sv = A->sv, M = A->M, nnz = A->nnz;
   const int64_t TW = A->ntiles * (int64_t)A->omega * A->c5sigma;
   struct Entry {
@@ -219,7 +235,7 @@ static spmv_status_t lookup(spmv_mat_t A, const char* name, const void** p, size
     const void* p;
     int64_t b;
   } tab[] = {
-      {"ptr", A->fmt == SPMV_FMT_CSR || A->fmt == SPMV_FMT_CSR5, A->ptr, 4 * (M + 1)},
+      {"ptr", (A->fmt == SPMV_FMT_CSR || A->fmt == SPMV_FMT_CSR5) && own, A->ptr, 4 * (M + 1)},
       {"band_ptr", A->nbands > 0, A->bptr, 4 * (int64_t)A->nbands * (M + 1)},
       {"band_col", A->nbands > 0, A->bcol, 4 * nnz},
       {"band_val", A->nbands > 0, A->bval, sv * nnz},
@@ -227,21 +243,21 @@ static spmv_status_t lookup(spmv_mat_t A, const char* name, const void** p, size
       {"val", A->fmt == SPMV_FMT_CSR, A->val, sv * nnz},
       {"ell_col", A->fmt == SPMV_FMT_ELL || A->fmt == SPMV_FMT_HYB, A->ecol, 4 * M * A->K},
       {"ell_val", A->fmt == SPMV_FMT_ELL || A->fmt == SPMV_FMT_HYB, A->eval, sv * M * A->K},
-      {"sell_perm", A->fmt == SPMV_FMT_SELL && A->perm, A->perm, 4 * A->Mpad},
-      {"sell_cs", A->fmt == SPMV_FMT_SELL, A->cs, 8 * (A->nchunks + 1)},
-      {"sell_col", A->fmt == SPMV_FMT_SELL, A->scol, 4 * A->nslots},
-      {"sell_val", A->fmt == SPMV_FMT_SELL, A->sval, sv * A->nslots},
+      {"sell_perm", sell && A->perm, A->perm, 4 * A->Mpad},
+      {"sell_cs", sell, A->cs, 8 * (A->nchunks + 1)},
+      {"sell_col", sell, A->scol, 4 * A->nslots},
+      {"sell_val", sell, A->sval, sv * A->nslots},
       {"coo_row", A->fmt == SPMV_FMT_HYB, A->crow, 4 * A->ncoo},
       {"coo_col", A->fmt == SPMV_FMT_HYB, A->ccol, 4 * A->ncoo},
       {"coo_val", A->fmt == SPMV_FMT_HYB, A->cval, sv * A->ncoo},
-      {"tile_ptr", A->fmt == SPMV_FMT_CSR5, A->tile_ptr, 4 * (A->ntiles + 1)},
-      {"bit_flag", A->fmt == SPMV_FMT_CSR5, A->bit_flag, 4 * A->ntiles * A->omega},
-      {"y_off", A->fmt == SPMV_FMT_CSR5, A->y_off, 4 * A->ntiles * A->omega},
-      {"seg_off", A->fmt == SPMV_FMT_CSR5, A->seg_off, 4 * A->ntiles * A->omega},
-      {"tile_col", A->fmt == SPMV_FMT_CSR5, A->col, 4 * TW},
-      {"tile_val", A->fmt == SPMV_FMT_CSR5, A->val, sv * TW},
-      {"tail_col", A->fmt == SPMV_FMT_CSR5, A->col ? (const void*)(A->col + TW) : nullptr, 4 * (nnz - TW)},
-      {"tail_val", A->fmt == SPMV_FMT_CSR5, A->val ? (const void*)((const char*)A->val + sv * TW) : nullptr,
+      {"tile_ptr", A->fmt == SPMV_FMT_CSR5 && own, A->tile_ptr, 4 * (A->ntiles + 1)},
+      {"bit_flag", A->fmt == SPMV_FMT_CSR5 && own, A->bit_flag, 4 * A->ntiles * A->omega},
+      {"y_off", A->fmt == SPMV_FMT_CSR5 && own, A->y_off, 4 * A->ntiles * A->omega},
+      {"seg_off", A->fmt == SPMV_FMT_CSR5 && own, A->seg_off, 4 * A->ntiles * A->omega},
+      {"tile_col", A->fmt == SPMV_FMT_CSR5 && own, A->col, 4 * TW},
+      {"tile_val", A->fmt == SPMV_FMT_CSR5 && own, A->val, sv * TW},
+      {"tail_col", A->fmt == SPMV_FMT_CSR5 && own, A->col ? (const void*)(A->col + TW) : nullptr, 4 * (nnz - TW)},
+      {"tail_val", A->fmt == SPMV_FMT_CSR5 && own, A->val ? (const void*)((const char*)A->val + sv * TW) : nullptr,
        sv * (nnz - TW)},
   };
   for (const Entry& e : tab)

@@ -126,6 +126,7 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
   hipStream_t st = hs(s);
   spmv_params_t base;
   resolve_params(inout, &base);
+  base.bands = 1;  // the candidates below set their own
   uint64_t h = 0;
   SPMV_TRY(structure_hash(csr, &h, st));
   const TuneKey key(h, csr->M, csr->N, csr->nnz, (int)csr->dt, (int)fmt, base.max_bytes);
@@ -137,6 +138,17 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       if (ms_out) *ms_out = it->second.second;
       return SPMV_OK;
     }
+  }
+  // x larger than 8 MiB: column bands holding at most 8 MiB of x each (at
+  // most 8) are candidates too.  Random gathers from a slice that fits the
+  // L2s cost about half those served from the Infinity Cache, but each band
+  // adds launches and an M-long partial product; measured, bands paid off
+  // from about 16 MB of x on and not at 8 MB.
+  int xbands = 1;
+  {
+    const int64_t xb = csr->N * (int64_t)csr->sv, slice = (int64_t)8 << 20;
+    while (xbands < 8 && xb > slice * xbands) xbands *= 2;
+    if (csr->M == 0) xbands = 1;
   }
   std::vector<spmv_params_t> cand;
   auto add = [&](auto&& f) {
@@ -159,14 +171,29 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       for (int V : {4, 8, 16, 32}) add([V](spmv_params_t& p) { p.csr_lanes_per_row = V; });
       break;
     case SPMV_FMT_CSR5:
-      for (int sg : {4, 8, 16, 32}) add([sg](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; });
+      for (int sg : {4, 8, 16, 32}) add([sg](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = 1; });
+      if (xbands > 1)
+        for (int sg : {16, 32})
+          add([sg, xbands](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = xbands; });
       break;
     case SPMV_FMT_ELL:
       add([](spmv_params_t&) {});
       break;
     case SPMV_FMT_SELL:
-      for (int C : {8, 16, 32, 64})
-        for (int sg : {1, C, 8 * C, 256 * C}) add([C, sg](spmv_params_t& p) { p.sell_C = C; p.sell_sigma = sg; });
+      // sigma in {1, C, 8C, 256C} and one window over all rows (a global
+      // sort by length, which removes nearly all padding of skewed rows)
+      for (int C : {8, 16, 32, 64}) {
+        const int64_t all = std::max<int64_t>(csr->M, 1);
+        for (int64_t sg : {(int64_t)1, (int64_t)C, (int64_t)8 * C, (int64_t)256 * C, all}) {
+          if (sg == all && all <= (int64_t)256 * C) continue;  // 256C already covers every row
+          add([C, sg](spmv_params_t& p) { p.sell_C = C; p.sell_sigma = (int32_t)sg; p.bands = 1; });
+        }
+      }
+      if (xbands > 1) {
+        const int32_t all = (int32_t)std::min<int64_t>(csr->M, INT32_MAX);
+        for (int C : {32, 64})
+          add([C, all, xbands](spmv_params_t& p) { p.sell_C = C; p.sell_sigma = all; p.bands = xbands; });
+      }
       break;
     case SPMV_FMT_HYB: {
       // K from the rule, and the 50/75/90/99th percentiles of the row lengths

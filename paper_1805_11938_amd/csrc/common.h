@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -160,6 +161,8 @@ struct spmv_mat_s {
   void* sval = nullptr;
   int64_t nitems = 0, nwide = 0;  // column-slice work items; chunks split into several slices
   int32_t sell_maxw = 0;          // widest chunk (= longest row)
+  int64_t kc_first = 0;           // chunks [kc_first, nchunks) are at most SELL_KC_MAX wide (one-pass kernel);
+  int32_t kc_w = 0;               // the widest of them; chunks before kc_first go through the slice items
   int2* items = nullptr;          // (chunk, first column) per item
   int4* wide = nullptr;           // (chunk, first item, item count) per split chunk
   double* part = nullptr;         // nitems * C partial sums (run scratch, split chunks only)
@@ -189,6 +192,12 @@ struct spmv_mat_s {
   int64_t nchains = 0;
   int32_t* chains = nullptr;     // (row, t_begin, t_end) triples for the carry fix-up
   double* carry = nullptr;       // ntiles + 1 partial sums (run scratch)
+
+  // Column bands (params.bands > 1, SELL and CSR5): sub[b] is the handle's
+  // format built from the entries with col in [b*band_w, (b+1)*band_w), over
+  // all M rows; this handle holds no format arrays of its own
+  std::vector<std::unique_ptr<spmv_mat_s>> sub;
+  void* spart = nullptr;  // bands x M band products in the value type (run scratch)
 
   int64_t bytes_fmt = 0, pad_slots = 0;
 
@@ -224,6 +233,11 @@ spmv_status_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 // ------------------------------------------------------------- builders
 spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s);
 spmv_status_t csr_build_bands(spmv_mat_s* A, hipStream_t s);
+// Splits src's entries by column band (band b: col in [b*bw, (b+1)*bw)) into
+// nb CSRs of all M rows: bptr is nb x (M+1), each relative to its band's first
+// entry off[b]; bcol / bval hold the bands one after another.
+spmv_status_t csr_split_bands(const spmv_mat_s* src, int nb, int64_t bw, int32_t* bptr, int32_t* bcol, void* bval,
+                              std::vector<int64_t>& off, hipStream_t s);
 spmv_status_t convert_ell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
 spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
 spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
@@ -238,6 +252,9 @@ spmv_status_t run_hyb(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
 spmv_status_t run_csr5(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
 spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s);
 spmv_status_t dispatch_run(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
+spmv_status_t run_banded(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
+spmv_status_t banded_to_csr(spmv_mat_s* A, int32_t* ptr, int32_t* col, void* val, hipStream_t s);
 
 spmv_status_t mat_alloc(spmv_mat_s* A, void** p, size_t bytes);
 void resolve_params(const spmv_params_t* in, spmv_params_t* out);

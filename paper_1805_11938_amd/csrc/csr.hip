@@ -307,12 +307,12 @@ __global__ void k_csr_band_sum(int64_t M, const double* __restrict__ part, T* __
   }
 }
 
-// entries of each row in each band (columns are sorted: binary searches)
-__global__ void k_band_count(int64_t M, const int32_t* ptr, const int32_t* col, int64_t bw, int32_t* cnt) {
+// entries of each row in each of nb bands (columns are sorted: binary searches)
+__global__ void k_band_count(int64_t M, const int32_t* ptr, const int32_t* col, int64_t bw, int nb, int32_t* cnt) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a = ptr[r], e = ptr[r + 1];
     int64_t prev = a;
-    for (int b = 0; b < NBANDS; ++b) {
+    for (int b = 0; b < nb; ++b) {
       int64_t lo = prev, hi = e;  // first entry with col >= (b+1)*bw
       const int64_t lim = (b + 1) * bw;
       while (lo < hi) {
@@ -327,11 +327,11 @@ __global__ void k_band_count(int64_t M, const int32_t* ptr, const int32_t* col, 
 }
 
 template <typename T>
-__global__ void k_band_scatter(int64_t M, const int32_t* ptr, const int32_t* col, const T* val, const int32_t* cnt,
-                               const int32_t* bptr, const int64_t* boff, int32_t* bcol, T* bval) {
+__global__ void k_band_scatter(int64_t M, int nb, const int32_t* ptr, const int32_t* col, const T* val,
+                               const int32_t* cnt, const int32_t* bptr, const int64_t* boff, int32_t* bcol, T* bval) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
     int64_t k = ptr[r];
-    for (int b = 0; b < NBANDS; ++b) {
+    for (int b = 0; b < nb; ++b) {
       const int64_t dst = boff[b] + bptr[b * (M + 1) + r];
       const int32_t n = cnt[b * M + r];
       for (int32_t q = 0; q < n; ++q) {
@@ -343,38 +343,46 @@ __global__ void k_band_scatter(int64_t M, const int32_t* ptr, const int32_t* col
   }
 }
 
+spmv_status_t csr_split_bands(const spmv_mat_s* src, int nb, int64_t bw, int32_t* bptr, int32_t* bcol, void* bval,
+                              std::vector<int64_t>& off, hipStream_t s) {
+  const int64_t M = src->M;
+  DTmp cnt, doff;
+  SPMV_TRY(cnt.alloc(sizeof(int32_t) * nb * std::max<int64_t>(M, 1)));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M, BS), 65536));
+  if (M) {
+    k_band_count<<<g, BS, 0, s>>>(M, src->ptr, src->col, bw, nb, cnt.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+  }
+  off.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    SPMV_TRY(scan_i32_to_i32(cnt.as<int32_t>() + b * M, bptr + b * (M + 1), M, s));
+    int32_t n = 0;
+    SPMV_TRY(copy_to_host(&n, bptr + b * (M + 1) + M, sizeof(int32_t), s));
+    off[b + 1] = off[b] + n;
+  }
+  SPMV_TRY(doff.alloc(sizeof(int64_t) * (nb + 1)));
+  SPMV_HIP(hipMemcpyAsync(doff.p, off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
+  if (M) {
+    if (src->dt == SPMV_F64)
+      k_band_scatter<double><<<g, BS, 0, s>>>(M, nb, src->ptr, src->col, (const double*)src->val, cnt.as<int32_t>(),
+                                              bptr, doff.as<int64_t>(), bcol, (double*)bval);
+    else
+      k_band_scatter<float><<<g, BS, 0, s>>>(M, nb, src->ptr, src->col, (const float*)src->val, cnt.as<int32_t>(),
+                                             bptr, doff.as<int64_t>(), bcol, (float*)bval);
+    SPMV_LAUNCH_CHECK();
+  }
+  SPMV_HIP(hipStreamSynchronize(s));  // cnt and doff are freed on return
+  return SPMV_OK;
+}
+
 spmv_status_t csr_build_bands(spmv_mat_s* A, hipStream_t s) {
   const int64_t M = A->M;
   A->nbands = NBANDS;
   A->band_w = std::max<int64_t>(1, cdiv(A->N, NBANDS));
-  DTmp cnt, doff;
-  SPMV_TRY(cnt.alloc(sizeof(int32_t) * NBANDS * std::max<int64_t>(M, 1)));
   SPMV_TRY(mat_alloc(A, (void**)&A->bptr, sizeof(int32_t) * NBANDS * (M + 1)));
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(M, BS), 65536));
-  if (M) {
-    k_band_count<<<g, BS, 0, s>>>(M, A->ptr, A->col, A->band_w, cnt.as<int32_t>());
-    SPMV_LAUNCH_CHECK();
-  }
-  A->band_off.assign(NBANDS + 1, 0);
-  for (int b = 0; b < NBANDS; ++b) {
-    SPMV_TRY(scan_i32_to_i32(cnt.as<int32_t>() + b * M, A->bptr + b * (M + 1), M, s));
-    int32_t nb = 0;
-    SPMV_TRY(copy_to_host(&nb, A->bptr + b * (M + 1) + M, sizeof(int32_t), s));
-    A->band_off[b + 1] = A->band_off[b] + nb;
-  }
   SPMV_TRY(mat_alloc(A, (void**)&A->bcol, sizeof(int32_t) * A->nnz));
   SPMV_TRY(mat_alloc(A, &A->bval, (size_t)A->sv * A->nnz));
-  SPMV_TRY(doff.alloc(sizeof(int64_t) * (NBANDS + 1)));
-  SPMV_HIP(hipMemcpyAsync(doff.p, A->band_off.data(), sizeof(int64_t) * (NBANDS + 1), hipMemcpyHostToDevice, s));
-  if (M) {
-    if (A->dt == SPMV_F64)
-      k_band_scatter<double><<<g, BS, 0, s>>>(M, A->ptr, A->col, (const double*)A->val, cnt.as<int32_t>(), A->bptr,
-                                              doff.as<int64_t>(), A->bcol, (double*)A->bval);
-    else
-      k_band_scatter<float><<<g, BS, 0, s>>>(M, A->ptr, A->col, (const float*)A->val, cnt.as<int32_t>(), A->bptr,
-                                             doff.as<int64_t>(), A->bcol, (float*)A->bval);
-    SPMV_LAUNCH_CHECK();
-  }
+  SPMV_TRY(csr_split_bands(A, NBANDS, A->band_w, A->bptr, A->bcol, A->bval, A->band_off, s));
   // row blocks of each band (the same merged rows + nonzeros split)
   A->band_nblk.assign(NBANDS, 0);
   A->band_blk0.assign(NBANDS + 1, 0);

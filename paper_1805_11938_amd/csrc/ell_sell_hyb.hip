@@ -395,6 +395,7 @@ __global__ void k_sell_to_csr(int64_t M, int64_t Mpad, int C, const int32_t* per
 // lanes (one per stored row).  Chunks of one slice write y directly; wider
 // chunks write per-slice partial sums that k_sell_fix adds in slice order.
 constexpr int SELL_KT = 64;
+constexpr int SELL_KC_MAX = 32;  // widest chunk the one-pass narrow kernel takes
 
 template <typename T, int LOGC, bool PERM>
 __global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const int2* __restrict__ items,
@@ -449,21 +450,45 @@ __global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const in
   }
 }
 
-// Narrow SELL (every chunk at most KC wide): one lane per stored row, one
-// pass over the chunks (no persistent loop), every slot's column and value
-// load in flight at once, then every gather, then the sum.  Places w..KC-1
-// of a chunk of width w reload slot w-1 (same address) and are masked.
+// The slots of one stored row, KW places (KW >= w): every slot's column and
+// value load in flight at once, then every gather, then the sum.  Places
+// w..KW-1 reload slot w-1 (same address) and are masked.
+template <typename T, int LOGC, int KW>
+__device__ __forceinline__ void sell_slots(const int32_t* __restrict__ cc, const T* __restrict__ vv,
+                                           const T* __restrict__ x, int w, double* sa) {
+  constexpr int C = 1 << LOGC;
+  int32_t cg[KW];
+  T vg[KW], xg[KW];
+#pragma unroll
+  for (int u = 0; u < KW; ++u) cg[u] = ldnt32(cc, (uint32_t)((u < w ? u : w - 1) * C));
+#pragma unroll
+  for (int u = 0; u < KW; ++u) vg[u] = ldnt32(vv, (uint32_t)((u < w ? u : w - 1) * C));
+  issue_fence();
+#pragma unroll
+  for (int u = 0; u < KW; ++u) xg[u] = ld32(x, (uint32_t)(cg[u] >= 0 ? cg[u] : 0));
+  issue_fence();
+#pragma unroll
+  for (int u = 0; u < KW; ++u) sa[u & 3] += (u < w && cg[u] >= 0) ? (double)vg[u] * (double)xg[u] : 0.0;
+}
+
+// Narrow SELL (chunks [c0, nchunks), each at most KC wide): one lane per
+// stored row, one pass over the chunks (no persistent loop).  A chunk runs
+// in the smallest of 4, 8, 16 and KC places that holds its width (with
+// C = 64 the width is the same for the whole wave, so this is a uniform
+// branch): chunks much narrower than KC issue no redundant loads.
 template <typename T, int LOGC, bool PERM, int KC>
-__global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t nchunks, const int64_t* __restrict__ cs,
+__global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t c0, int64_t nchunks, const int64_t* __restrict__ cs,
                                                   const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
                                                   const T* __restrict__ sval, const T* __restrict__ x,
-                                                  T* __restrict__ y) {
+                                                  T* __restrict__ y, int remap) {
   constexpr int C = 1 << LOGC;
-  // one wave per workgroup (the finest unit the dispatcher balances); each
-  // XCD takes a contiguous range of chunks (neighbouring rows share x in its L2)
-  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WAVE + threadIdx.x;
+  // one wave per workgroup (the finest unit the dispatcher balances).  With
+  // remap each XCD takes a contiguous range of chunks (neighbouring rows
+  // share x in its L2); without it chunks go round-robin over the XCDs, which
+  // balances a chunk list sorted by width over long windows.
+  const int64_t gid = (int64_t)(remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * WAVE + threadIdx.x;
   // C = 64: one chunk per wave, so its offsets are scalar loads
-  const int64_t c = LOGC == 6 ? (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(gid >> 6)) : gid >> LOGC;
+  const int64_t c = c0 + (LOGC == 6 ? (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(gid >> 6)) : gid >> LOGC);
   if (c >= nchunks) return;
   const int p = (int)(gid & (C - 1));
   const int64_t base = cs[c];
@@ -472,18 +497,10 @@ __global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t nchunks, co
   if (w > 0) {
     const int32_t* cc = scol + base + p;
     const T* vv = sval + base + p;
-    int32_t cg[KC];
-    T vg[KC], xg[KC];
-#pragma unroll
-    for (int u = 0; u < KC; ++u) cg[u] = ldnt32(cc, (uint32_t)((u < w ? u : w - 1) * C));
-#pragma unroll
-    for (int u = 0; u < KC; ++u) vg[u] = ldnt32(vv, (uint32_t)((u < w ? u : w - 1) * C));
-    issue_fence();
-#pragma unroll
-    for (int u = 0; u < KC; ++u) xg[u] = ld32(x, (uint32_t)(cg[u] >= 0 ? cg[u] : 0));
-    issue_fence();
-#pragma unroll
-    for (int u = 0; u < KC; ++u) sa[u & 3] += (u < w && cg[u] >= 0) ? (double)vg[u] * (double)xg[u] : 0.0;
+    if (KC > 16 && w > 16) sell_slots<T, LOGC, KC>(cc, vv, x, w, sa);
+    else if (KC > 8 && w > 8) sell_slots<T, LOGC, (KC < 16 ? KC : 16)>(cc, vv, x, w, sa);
+    else if (KC > 4 && w > 4) sell_slots<T, LOGC, (KC < 8 ? KC : 8)>(cc, vv, x, w, sa);
+    else sell_slots<T, LOGC, (KC < 4 ? KC : 4)>(cc, vv, x, w, sa);
   }
   const int64_t pos = c * C + p;
   const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
@@ -499,8 +516,20 @@ __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restri
   if (wi >= nwide) return;
   const int p = (int)(gid % C);
   const int4 wd = wide[wi];  // chunk, first item, item count
-  double s = 0.0;
-  for (int i = 0; i < wd.z; ++i) s += part[((int64_t)wd.y + i) * C + p];
+  // eight running sums (slice i goes to sum i mod 8) keep eight loads in
+  // flight on the longest chunks; they are combined in a fixed order
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const double* q = part + (int64_t)wd.y * C + p;
+  int i = 0;
+  for (; i + 8 <= wd.z; i += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = q[(int64_t)(i + u) * C];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u];
+  }
+  for (int u = 0; i < wd.z; ++i, ++u) a[u] += q[(int64_t)i * C];
+  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   const int64_t pos = (int64_t)wd.x * C + p;
   const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
   if (r >= 0) y[r] = (T)s;
@@ -508,20 +537,26 @@ __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restri
 
 template <typename T, int LOGC, int KC>
 static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  const unsigned g = (unsigned)cdiv(A->nchunks << LOGC, WAVE);
+  const unsigned g = (unsigned)cdiv((A->nchunks - A->kc_first) << LOGC, WAVE);
+  // contiguous ranges per XCD only while a sort window is small next to an
+  // XCD's share of the rows (chunk widths then do not trend across the list)
+  const int remap = (int64_t)A->sigma * 8 <= A->M;
   if (A->perm)
-    launch(k_sell_kc<T, LOGC, true, KC>, g, WAVE, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
-           (const T*)x, (T*)y);
+    launch(k_sell_kc<T, LOGC, true, KC>, g, WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+           (const T*)A->sval, (const T*)x, (T*)y, remap);
   else
-    launch(k_sell_kc<T, LOGC, false, KC>, g, WAVE, s, A->M, A->nchunks, A->cs, A->perm, A->scol, (const T*)A->sval,
-           (const T*)x, (T*)y);
+    launch(k_sell_kc<T, LOGC, false, KC>, g, WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+           (const T*)A->sval, (const T*)x, (T*)y, remap);
 }
 
+// Chunks [kc_first, nchunks) (at most SELL_KC_MAX wide) go through the one-pass
+// narrow kernel; the chunks before them (with a global sort: the longest
+// rows) through the column-slice items.  Both write disjoint rows of y.
 template <typename T, int LOGC>
 static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  if (LOGC >= 3 && A->sell_maxw <= 32 && !(A->params.flags & SPMV_FLAG_SELL_SLICES)) {
+  if (A->kc_first < A->nchunks) {
     if (LOGC == 6) {  // one chunk per wave: instantiated for the exact widest chunk
-      switch (A->sell_maxw) {
+      switch (A->kc_w) {
       case 1: launch_sell_kc<T, 6, 1>(A, x, y, s); break;
       case 2: launch_sell_kc<T, 6, 2>(A, x, y, s); break;
       case 3: launch_sell_kc<T, 6, 3>(A, x, y, s); break;
@@ -556,13 +591,13 @@ static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) 
       case 32: launch_sell_kc<T, 6, 32>(A, x, y, s); break;
         default: launch_sell_kc<T, 6, 32>(A, x, y, s); break;  // maxw == 0: nothing to load
       }
-    } else if (A->sell_maxw <= 16) {
+    } else if (A->kc_w <= 16) {
       launch_sell_kc<T, LOGC, 16>(A, x, y, s);
     } else {
       launch_sell_kc<T, LOGC, 32>(A, x, y, s);
     }
-    return;
   }
+  if (A->kc_first == 0) return;
   const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nitems << LOGC, BS), resident_blocks(8));
   if (A->perm)
     launch(k_sell<T, LOGC, true>, g, BS, s, A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
@@ -599,6 +634,19 @@ static spmv_status_t run_sell_t(spmv_mat_s* A, const void* x, void* y, hipStream
 spmv_status_t run_sell(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   if (A->dt == SPMV_F64) return run_sell_t<double>(A, x, y, s);
   return run_sell_t<float>(A, x, y, s);
+}
+
+// out[0] = 1 + the last chunk wider than SELL_KC_MAX (0 if none)
+__global__ void k_sell_lastwide(int64_t nch, int C, const int64_t* cs, int32_t* out) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x)
+    if ((cs[c + 1] - cs[c]) / C > SELL_KC_MAX) atomicMax(out, (int32_t)(c + 1));
+}
+
+// out[1] = the widest chunk from out[0] on
+__global__ void k_sell_tailw(int64_t nch, int C, const int64_t* cs, int32_t* out) {
+  const int64_t c0 = out[0];
+  for (int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x)
+    atomicMax(out + 1, (int32_t)((cs[c + 1] - cs[c]) / C));
 }
 
 // slices per chunk, and the item / wide-chunk lists
@@ -674,9 +722,27 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
                                                A->perm, A->cs, A->scol, (float*)A->sval);
     SPMV_LAUNCH_CHECK();
   }
-  // work items: column slices of at most SELL_KT per chunk
+  // the narrow tail of the chunk list (one-pass kernel): not with C < 8 or
+  // when the slice kernel is forced
+  A->kc_first = A->nchunks;
+  A->kc_w = 0;
+  if (C >= 8 && !(A->params.flags & SPMV_FLAG_SELL_SLICES) && A->nchunks > 0) {
+    DTmp kw;
+    SPMV_TRY(kw.alloc(2 * sizeof(int32_t)));
+    SPMV_HIP(hipMemsetAsync(kw.p, 0, 2 * sizeof(int32_t), s));
+    k_sell_lastwide<<<grid_rows(A->nchunks), BS, 0, s>>>(A->nchunks, C, A->cs, kw.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+    k_sell_tailw<<<grid_rows(A->nchunks), BS, 0, s>>>(A->nchunks, C, A->cs, kw.as<int32_t>());
+    SPMV_LAUNCH_CHECK();
+    int32_t h[2] = {0, 0};
+    SPMV_TRY(copy_to_host(h, kw.p, sizeof(h), s));
+    A->kc_first = h[0];
+    A->kc_w = h[1];
+  }
+  // work items: column slices of at most SELL_KT per chunk, for the chunks
+  // before kc_first
   {
-    const int64_t nch = A->nchunks;
+    const int64_t nch = A->kc_first;
     DTmp ns, wf, ib, wp;
     SPMV_TRY(ns.alloc(sizeof(int32_t) * std::max<int64_t>(nch, 1)));
     SPMV_TRY(wf.alloc(sizeof(int32_t) * std::max<int64_t>(nch, 1)));

@@ -385,8 +385,8 @@ def compare_classifiers(records, dtype="f64", test=None, seed=0):
     return out
 
 
-PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags"), "csr5": ("csr5_omega", "csr5_sigma"), "ell": (),
-              "sell": ("sell_C", "sell_sigma"), "hyb": ("hyb_K",)}
+PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags"), "csr5": ("csr5_omega", "csr5_sigma", "bands"), "ell": (),
+              "sell": ("sell_C", "sell_sigma", "bands"), "hyb": ("hyb_K",)}
 
 
 def merge(out_path, parts):
@@ -395,7 +395,7 @@ def merge(out_path, parts):
     recs = {}
     for p in parts:
         for r in load(p):
-            r["params"] = {f: (None if v is None else {k: v[k] for k in PARAM_KEYS[f]})
+            r["params"] = {f: (None if v is None else {k: v[k] for k in PARAM_KEYS[f] if k in v})
                            for f, v in r["params"].items()}
             recs[(r["index"], r["dtype"])] = r
     with open(out_path, "w") as fo:

@@ -34,7 +34,7 @@ class SpmvError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("sell_C", ctypes.c_int32), ("sell_sigma", ctypes.c_int32), ("csr_lanes_per_row", ctypes.c_int32),
                 ("hyb_K", ctypes.c_int32), ("csr5_omega", ctypes.c_int32), ("csr5_sigma", ctypes.c_int32),
-                ("max_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+                ("max_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32), ("bands", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -28,7 +28,8 @@ from . import synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "data", "tuned_params.json")
 FORMATS = ("csr", "csr5", "ell", "sell", "hyb")
-TUNE_KEYS = ("sell_C", "sell_sigma", "csr_lanes_per_row", "hyb_K", "csr5_omega", "csr5_sigma", "flags")
+TUNE_KEYS = ("sell_C", "sell_sigma", "csr_lanes_per_row", "hyb_K", "csr5_omega", "csr5_sigma", "flags",
+             "bands")
 
 X_SEED = {"stencil27_100": 3, "zipf_1M": 6, "rmat24": 11}
 

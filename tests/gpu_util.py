@@ -47,6 +47,8 @@ FORMAT_CONFIGS = [
     ("csr5", {"csr5_sigma": 4}),
     ("csr5", {"csr5_sigma": 32}),
     ("csr5", {"csr5_omega": 16, "csr5_sigma": 3}),
+    ("csr5", {"bands": 3}),
+    ("csr5", {"csr5_sigma": 4, "bands": 8}),
     ("ell", {}),
     ("ell", {"flags": 4}),
     ("sell", {}),
@@ -54,6 +56,9 @@ FORMAT_CONFIGS = [
     ("sell", {"sell_C": 64, "sell_sigma": 1}),
     ("sell", {"sell_C": 8, "sell_sigma": 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 16384}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "bands": 3}),
+    ("sell", {"sell_C": 8, "sell_sigma": 1, "bands": 8}),
+    ("sell", {"sell_C": 32, "sell_sigma": 64, "bands": 2, "flags": 8}),
     ("hyb", {}),
     ("hyb", {"hyb_K": 0}),
     ("hyb", {"hyb_K": 2}),

@@ -148,6 +148,38 @@ def test_device_conversions_bit_identical(torch, ci):
         assert np.array_equal(Sm.export("sell_val", np.float64).view(np.uint64), o["val"].view(np.uint64))
         if sg > 1 and M > 0:
             assert np.array_equal(Sm.export("sell_perm", np.int32), o["perm"])
+    # column bands: band b is the oracle's conversion of the entries with
+    # col in [b*w, (b+1)*w), w = ceil(N / bands), over all M rows
+    rows = np.repeat(np.arange(M), np.diff(A.ptr))
+
+    def band(b, w):
+        keep = (A.col >= b * w) & (A.col < (b + 1) * w)
+        bptr = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=M))]).astype(np.int32)
+        return bptr, A.col[keep], A.val[keep]
+
+    for C, sg, nb in [(64, 1 << 30, 3), (8, 1, 8)]:
+        Sm = Ad.convert("sell", sell_C=C, sell_sigma=sg, bands=nb)
+        w = -(-A.N // nb)
+        for b in range(nb):
+            o = oracle.csr_to_sell(M, *band(b, w), C, sg)
+            assert np.array_equal(Sm.export(f"band{b}.sell_cs", np.int64), o["cs"]), (name, nb, b)
+            assert np.array_equal(Sm.export(f"band{b}.sell_col", np.int32), o["col"]), (name, nb, b)
+            assert np.array_equal(Sm.export(f"band{b}.sell_val", np.float64).view(np.uint64),
+                                  o["val"].view(np.uint64)), (name, nb, b)
+            if sg > 1 and M > 0:
+                assert np.array_equal(Sm.export(f"band{b}.sell_perm", np.int32), o["perm"]), (name, nb, b)
+        with pytest.raises(S.SpmvError):
+            Sm.export("sell_col", np.int32)  # a banded handle has no arrays of its own
+    for sg, nb in [(16, 2), (4, 5)]:
+        C5 = Ad.convert("csr5", csr5_sigma=sg, bands=nb)
+        w = -(-A.N // nb)
+        for b in range(nb):
+            o = oracle.csr_to_csr5(M, *band(b, w), 64, sg)
+            for nm, dt_ in [("tile_ptr", np.int32), ("bit_flag", np.uint32), ("y_off", np.int32),
+                            ("seg_off", np.int32)]:
+                assert np.array_equal(C5.export(f"band{b}.{nm}", dt_), o[nm]), (name, nb, b, nm)
+            assert np.array_equal(C5.export(f"band{b}.tile_col", np.int32), o["col"]), (name, nb, b)
+            assert np.array_equal(C5.export(f"band{b}.tail_col", np.int32), o["tail_col"]), (name, nb, b)
     # HYB (rule and a fixed K)
     for Kh in (None, 1):
         o = oracle.csr_to_hyb(M, A.ptr, A.col, A.val, Kh)
@@ -243,6 +275,10 @@ def test_errors(torch):
     with pytest.raises(S.SpmvError) as e:
         S.Matrix.from_coo(2, 2, [0, 2], [0, 0], np.ones(2))
     assert e.value.status == -2
+    for fmt in ("csr", "ell", "hyb"):  # column bands are a SELL / CSR5 layout
+        with pytest.raises(S.SpmvError) as e:
+            A.convert(fmt, bands=2)
+        assert e.value.status == -5
     Z = S.Matrix.from_host(synth.zipf_rows(20_000, 20_000, 2.0, 16, 5_000, 4, 5))
     with pytest.raises(S.SpmvError) as e:
         Z.convert("ell", max_bytes=1 << 20)
