@@ -355,6 +355,13 @@ def main():
     roof = {"bound": "hbm", "achieved": dper["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(dper["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom["label"],
             "bytes_per_launch": int(dom["bytes"]), "ms_per_launch": dper["ms"]}
+    # the floor for as many gathers from an x of the same length with no
+    # locality at all (a balanced 16-per-row SpMV, uniformly random columns)
+    Nd = dom["m"].info.N
+    g_ms = S.gather_probe(Nd, -(-dom["nnz"] // 16), dt, reps=10, scrub_bytes=0 if args.warm else SCRUB)
+    roof["random_gather_floor"] = {"ms": round(g_ms, 5), "frac": round(g_ms / dper["ms"], 4),
+                                   "what": f"{16 * -(-dom['nnz'] // 16)} uniformly random gathers from x[{Nd}], "
+                                           f"16 per row, every load in flight (spmv_gather_probe)"}
     out = {"metric": "SpMV GB/s & % HBM roofline per format; selector % of best-format throughput vs CSR",
            "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1e3 * wall / args.steps, 4),

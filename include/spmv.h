@@ -205,6 +205,18 @@ spmv_status_t spmv_scrub(int64_t scrub_bytes, spmv_stream_t s);
  * reading and writing `bytes` each (median of reps). */
 spmv_status_t spmv_copy_probe(int64_t bytes, int reps, spmv_stream_t s, double* gbps);
 
+/* Random-gather probe: a perfectly balanced SpMV of `rows` rows with 16
+ * entries each whose columns are uniform over [0, nx) (a seeded SplitMix64
+ * hash), column and value arrays slot-major (coalesced), every load of a row
+ * in flight at once.  Its time is the floor for gathering 16 * rows entries
+ * from an x of nx values of dtype dt, the bound of launches limited by
+ * scattered gathers rather than by HBM bytes.  Allocates and frees its own
+ * buffers; times `reps` launches, each after a read-only scrub of
+ * scrub_bytes (0 = none), and writes the median in ms.  Synchronises s.
+ * INVALID_ARG unless 1 <= nx < 2^31 and 1 <= rows <= 2^27. */
+spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int reps, int64_t scrub_bytes,
+                                spmv_stream_t s, double* ms);
+
 /* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: V;
  * HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma; SELL sigma in
  * {1, C, 8C, 256C, M}, M being one window over all rows, and, when x exceeds

@@ -138,6 +138,47 @@ spmv_status_t time_run(spmv_mat_s* A, const void* x, void* y, int warmup, int mi
   return timed([&] { return dispatch_run(A, x, y, s); }, warmup, min_reps, max_reps, rel_ci, scrub_bytes, s, out);
 }
 
+// ------------------------------------------------------------ gather probe
+// A perfectly balanced SpMV without any locality in x: row i sums GP_J
+// products v * x[c] whose columns are uniform over [0, nx) (SplitMix64 of
+// the slot index and a seed), stored slot-major so the column and value
+// loads are coalesced, with every load of a row in flight at once.  Its time
+// is the floor for gathering that many entries from an x of nx values: the
+// roofline of launches bound by scattered gathers rather than by HBM bytes.
+constexpr int GP_J = 16;
+
+__global__ void k_gp_fill(int64_t total, uint64_t nx, uint64_t seed, int32_t* __restrict__ col) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)t * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    col[t] = (int32_t)(z % nx);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_gather_probe(int64_t rows, const int32_t* __restrict__ col,
+                                                     const T* __restrict__ val, const T* __restrict__ x,
+                                                     T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= rows) return;
+  int32_t c[GP_J];
+  T v[GP_J], xv[GP_J];
+#pragma unroll
+  for (int j = 0; j < GP_J; ++j) c[j] = ldnt(col + (int64_t)j * rows + i);
+#pragma unroll
+  for (int j = 0; j < GP_J; ++j) v[j] = ldnt(val + (int64_t)j * rows + i);
+  issue_fence();
+#pragma unroll
+  for (int j = 0; j < GP_J; ++j) xv[j] = x[c[j]];
+  issue_fence();
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < GP_J; ++j) s += (double)v[j] * (double)xv[j];
+  y[i] = (T)s;
+}
+
 }  // namespace spmv
 
 using namespace spmv;
@@ -173,6 +214,39 @@ spmv_status_t spmv_copy_probe(int64_t bytes, int reps, spmv_stream_t s, double* 
       },
       3, reps, reps, 0.0, 0, st, out));
   *gbps = 2.0 * (double)bytes / (out[0] * 1e-3) / 1e9;
+  return SPMV_OK;
+}
+
+spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int reps, int64_t scrub_bytes,
+                                spmv_stream_t s, double* ms) {
+  if (nx < 1 || nx >= ((int64_t)1 << 31) || rows < 1 || rows > ((int64_t)1 << 27) || !ms || reps < 1)
+    return fail(SPMV_ERR_INVALID_ARG, "gather probe: need 1 <= nx < 2^31, 1 <= rows <= 2^27, reps >= 1, ms");
+  if (dt != SPMV_F64 && dt != SPMV_F32) return fail(SPMV_ERR_INVALID_ARG, "dtype %d", (int)dt);
+  const int64_t sv = value_size(dt), total = rows * GP_J;
+  DTmp x, c, v, y;
+  SPMV_TRY(x.alloc((size_t)(nx * sv)));
+  SPMV_TRY(c.alloc((size_t)(total * 4)));
+  SPMV_TRY(v.alloc((size_t)(total * sv)));
+  SPMV_TRY(y.alloc((size_t)(rows * sv)));
+  hipStream_t st = hs(s);
+  SPMV_HIP(hipMemsetAsync(x.p, 0, (size_t)(nx * sv), st));
+  SPMV_HIP(hipMemsetAsync(v.p, 0, (size_t)(total * sv), st));
+  k_gp_fill<<<(unsigned)std::min<int64_t>(cdiv(total, BS), 8192), BS, 0, st>>>(total, (uint64_t)nx, 0x5EEDull,
+                                                                              c.as<int32_t>());
+  SPMV_LAUNCH_CHECK();
+  const unsigned g = (unsigned)cdiv(rows, BS);
+  double out[5];
+  SPMV_TRY(timed(
+      [&]() -> spmv_status_t {
+        if (dt == SPMV_F64)
+          k_gather_probe<double><<<g, BS, 0, st>>>(rows, c.as<int32_t>(), v.as<double>(), x.as<double>(), y.as<double>());
+        else
+          k_gather_probe<float><<<g, BS, 0, st>>>(rows, c.as<int32_t>(), v.as<float>(), x.as<float>(), y.as<float>());
+        SPMV_LAUNCH_CHECK();
+        return SPMV_OK;
+      },
+      2, reps, reps, 0.0, scrub_bytes, st, out));
+  *ms = out[0];
   return SPMV_OK;
 }
 

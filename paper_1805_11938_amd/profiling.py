@@ -12,8 +12,12 @@ Two uses:
   on a kernel whose traffic is known: the 1 GiB copy probe (1 GiB read,
   1 GiB written; ``bench.py --copy-probe``).
 
+* ``gather``: the random-gather floor (``spmv_gather_probe``) for x of
+  1, 4, 8 and 16 MB and 16.7 million gathers, FP64 and FP32 (needs the GPU).
+
     python -m paper_1805_11938_amd.profiling stats DIR/..._kernel_stats.csv
     python -m paper_1805_11938_amd.profiling traffic FETCH.csv WRITE.csv BENCH.json OUT.json
+    python -m paper_1805_11938_amd.profiling gather
 """
 from __future__ import annotations
 
@@ -122,6 +126,18 @@ def main(argv):
             else:
                 print(f"{k:40s} measured {v['bytes_per_launch'] / 1e6:10.1f} MB  algorithmic "
                       f"{v['algorithmic_bytes'] / 1e6:10.1f} MB  ratio {v['ratio']:.3f}")
+    elif argv[0] == "gather":
+        from . import spmv as S
+        rows = 1 << 20
+        print(f"random-gather floor: {16 * rows} gathers (16 per row, every load in flight), cold caches, "
+              f"median of 10")
+        print("| x bytes | x entries | dtype | ms | G gathers/s |")
+        print("|---|---|---|---|---|")
+        for dname, dt, sv in (("f64", S.F64, 8), ("f32", S.F32, 4)):
+            for mb in (1, 4, 8, 16):
+                nx = (mb << 20) // sv
+                ms = S.gather_probe(nx, rows, dt, reps=10)
+                print(f"| {mb} MiB | {nx} | {dname} | {ms:.4f} | {16 * rows / (ms * 1e-3) / 1e9:.1f} |", flush=True)
     else:
         raise SystemExit(__doc__)
 

@@ -58,6 +58,7 @@ EXPORTED = [
     "spmv_status_str", "spmv_last_error", "spmv_mat_from_csr", "spmv_mat_from_coo", "spmv_convert", "spmv_to_csr",
     "spmv_array_bytes", "spmv_export", "spmv_mat_info", "spmv_mat_free", "spmv_run", "spmv_spmm",
     "spmv_batch_create", "spmv_batch_run", "spmv_batch_free", "spmv_time", "spmv_scrub", "spmv_copy_probe",
+    "spmv_gather_probe",
     "spmv_autotune", "spmv_features", "spmv_model_create", "spmv_model_load", "spmv_model_save",
     "spmv_model_params", "spmv_model_free", "spmv_select", "spmv_mlp_forward", "spmv_mlp_backward", "spmv_mlp_adam",
     "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train", "spmv_run_timed", "spmv_spmm_timed",
@@ -94,6 +95,7 @@ def lib():
             "spmv_time": (st, [st, vp, vp, vp, st, st, st, dp, i64, vp, vp]),
             "spmv_scrub": (st, [i64, vp]),
             "spmv_copy_probe": (st, [i64, st, vp, ctypes.POINTER(dp)]),
+            "spmv_gather_probe": (st, [i64, i64, st, st, i64, vp, ctypes.POINTER(dp)]),
             "spmv_autotune": (st, [vp, st, vp, vp, i64, st, ctypes.POINTER(Params), ctypes.POINTER(dp), vp]),
             "spmv_features": (st, [vp, vp, vp]),
             "spmv_model_create": (st, [vp, vp, vp, ctypes.POINTER(vp)]),
@@ -314,6 +316,15 @@ def copy_probe(nbytes=1 << 30, reps=20) -> float:
     g = ctypes.c_double()
     check(lib().spmv_copy_probe(nbytes, reps, stream(), ctypes.byref(g)))
     return g.value
+
+
+def gather_probe(nx: int, rows: int, dtype: int = F64, reps: int = 10, scrub_bytes: int = 512 << 20) -> float:
+    """Median ms of a balanced 16-per-row SpMV with uniformly random columns
+    over an x of nx values: the floor for 16 * rows scattered gathers."""
+    ms = ctypes.c_double()
+    check(lib().spmv_gather_probe(int(nx), int(rows), int(dtype), int(reps), int(scrub_bytes), stream(),
+                                  ctypes.byref(ms)))
+    return ms.value
 
 
 # -------------------------------------------------------------- batches

@@ -74,3 +74,17 @@ def test_timed_spmm_batch_and_empty(torch):
     E.run_timed(xs[0][:4].contiguous(), torch.empty(0, dtype=torch.float64, device="cuda"), ev)
     torch.cuda.synchronize()
     assert ev[0].elapsed_time(ev[1]) >= 0
+
+
+def test_gather_probe_sees_the_cache_levels(torch):
+    """The random-gather floor: positive, and gathers from an x that fits an
+    XCD's L2 (1 MiB) are clearly cheaper than from one that only fits the
+    Infinity Cache (16 MiB).  Bad sizes are rejected."""
+    small = S.gather_probe(1 << 17, 1 << 20, S.F64, reps=5)
+    big = S.gather_probe(1 << 21, 1 << 20, S.F64, reps=5)
+    assert 0 < small < 0.8 * big, (small, big)
+    assert S.gather_probe(1 << 17, 1 << 16, S.F32, reps=3) > 0
+    for nx, rows in [(0, 10), (10, 0), (1 << 31, 10), (10, (1 << 27) + 1)]:
+        with pytest.raises(S.SpmvError) as e:
+            S.gather_probe(nx, rows, S.F64, reps=1)
+        assert e.value.status == -1
