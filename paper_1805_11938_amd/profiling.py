@@ -30,7 +30,7 @@ SCRUB = "k_scrub"
 COPY = "k_copy"
 # kernels that spmv_run launches (conversion, feature and selection kernels
 # run outside the scrubbed launches and are not counted)
-RUN_KERNELS = ("k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix",
+RUN_KERNELS = ("k_band_sum", "k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix",
                "k_c5_zero", "k_ell", "k_ell2", "k_ell_kc", "k_sell", "k_sell_kc", "k_sell_fix", "k_coo")
 
 
@@ -127,7 +127,9 @@ def main(argv):
                 print(f"{k:40s} measured {v['bytes_per_launch'] / 1e6:10.1f} MB  algorithmic "
                       f"{v['algorithmic_bytes'] / 1e6:10.1f} MB  ratio {v['ratio']:.3f}")
     elif argv[0] == "gather":
+        import torch
         from . import spmv as S
+        assert torch.cuda.is_available(), "the gather probe needs the GPU"
         rows = 1 << 20
         print(f"random-gather floor: {16 * rows} gathers (16 per row, every load in flight), cold caches, "
               f"median of 10")

@@ -73,6 +73,11 @@ def lib():
     if _L is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: the HIP library must be built (__graft_entry__.build())")
+        # torch first: it loads the HIP runtime it ships with, and the library
+        # then binds to that one (same soname).  Loaded the other way round a
+        # process would hold two HIP runtimes, and the second to initialise
+        # finds no device.  (Importing torch does not touch the GPU.)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         i32, i64, u32, vp, dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_double
         st = ctypes.c_int
