@@ -607,22 +607,31 @@ spmv_status_t run_csr(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
 // ----------------------------------------------------------------- SpMM
 // Y = A X for k right-hand sides (row-major, k <= 64).  Same row blocks as
 // the SpMV kernel; the block's col/val are staged in LDS once and reused by
-// all k columns.  Thread t works on column c = t % k of rows t / k,
-// t / k + G, ... (G = 256 / k): the k threads of a row read k consecutive
-// values of X per nonzero and write k consecutive values of Y.
+// all k columns.  A lane owns VEC consecutive columns of one row: lanes
+// t / (k/VEC), ... take rows, so the k/VEC lanes of a row read its k values
+// of X per nonzero as k/VEC loads of VEC values (16 bytes when VEC > 1) and
+// write k consecutive values of Y.  VEC > 1 needs k, ldx and ldy multiples
+// of VEC and 16-byte aligned X and Y; otherwise VEC = 1.
 constexpr int SPMM_CAP = 2048;
 
-template <typename T>
+template <typename T, int VEC>
+struct alignas(sizeof(T) * VEC) VecN {
+  T v[VEC];
+};
+
+template <typename T, int VEC>
 __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __restrict__ blk_row,
                                                  const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                  const T* __restrict__ val, const T* __restrict__ X, int64_t ldx,
                                                  T* __restrict__ Y, int64_t ldy, int k) {
+  typedef VecN<T, VEC> V;
   __shared__ int32_t scol[SPMM_CAP];
   __shared__ T sval[SPMM_CAP];
-  __shared__ double red[BS];
+  __shared__ double red[BS * VEC];
   const int t = threadIdx.x;
-  const int G = BS / k;
-  const int g = t / k, c = t % k;
+  const int kv = k / VEC;  // lanes per row
+  const int G = BS / kv;
+  const int g = t / kv, c = (t % kv) * VEC;
   {  // one workgroup per row block, each XCD a contiguous range of blocks
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= nblk) return;
@@ -653,13 +662,18 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
       if (g < G)
         for (int64_t r = r0 + g; r < r1; r += G) {
           const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
-          double s4[4] = {0.0, 0.0, 0.0, 0.0};
+          double s4[4][VEC];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s4[i][v] = 0.0;
           // 16 nonzeros at a time, all 16 gathers of X rows in flight; the
           // last group repeats entry e-1 for its unused places and masks them
           for (int q = a; q < e; q += 16) {
             const int n = e - q < 16 ? e - q : 16;
             int32_t cq[16];
-            T vq[16], xq[16];
+            T vq[16];
+            V xq[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
               const int qq = q + (u < n ? u : n - 1);
@@ -667,11 +681,16 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
               vq[u] = sval[qq];
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) xq[u] = X[(int64_t)cq[u] * ldx + c];
+            for (int u = 0; u < 16; ++u) xq[u] = *(const V*)(X + (int64_t)cq[u] * ldx + c);
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s4[u & 3] += u < n ? (double)vq[u] * (double)xq[u] : 0.0;
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) s4[u & 3][v] += u < n ? (double)vq[u] * (double)xq[u].v[v] : 0.0;
           }
-          Y[r * ldy + c] = (T)((s4[0] + s4[1]) + (s4[2] + s4[3]));
+          V out;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) out.v[v] = (T)((s4[0][v] + s4[1][v]) + (s4[2][v] + s4[3][v]));
+          *(V*)(Y + r * ldy + c) = out;
         }
       __syncthreads();
     } else {
@@ -679,15 +698,28 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
       // ordered sum of the groups' partials in LDS
       for (int64_t r = r0; r < r1; ++r) {
         const int64_t a = ptr[r], e = ptr[r + 1];
-        double s = 0.0;
+        double sv[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) sv[v] = 0.0;
         if (g < G)
-          for (int64_t q = a + g; q < e; q += G) s += (double)ldnt(val + q) * (double)X[(int64_t)ldnt(col + q) * ldx + c];
-        red[t] = s;
+          for (int64_t q = a + g; q < e; q += G) {
+            const double w = (double)ldnt(val + q);
+            const V xv = *(const V*)(X + (int64_t)ldnt(col + q) * ldx + c);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) sv[v] += w * (double)xv.v[v];
+          }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) red[t * VEC + v] = sv[v];
         __syncthreads();
         if (g == 0) {
-          double tot = 0.0;
-          for (int gg = 0; gg < G; ++gg) tot += red[gg * k + c];
-          Y[r * ldy + c] = (T)tot;
+          V out;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            double tot = 0.0;
+            for (int gg = 0; gg < G; ++gg) tot += red[(gg * kv + t % kv) * VEC + v];
+            out.v[v] = (T)tot;
+          }
+          *(V*)(Y + r * ldy + c) = out;
         }
         __syncthreads();
       }
@@ -695,17 +727,29 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
   }
 }
 
+template <typename T, int VEC>
+static void launch_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {
+  launch(k_csr_spmm<T, VEC>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const T*)A->val,
+         (const T*)X, ldx, (T*)Y, ldy, k);  // one workgroup per row block
+}
+
 spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {
   if (A->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_UNSUPPORTED, "spmm runs on CSR handles");
   if (k < 1 || k > 64 || ldx < k || ldy < k) return fail(SPMV_ERR_INVALID_ARG, "spmm needs 1 <= k <= 64, ld >= k");
   if (A->M == 0) return SPMV_OK;
-  const unsigned g = (unsigned)A->nblk;  // one workgroup per row block
-  if (A->dt == SPMV_F64)
-    launch(k_csr_spmm<double>, g, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const double*)A->val,
-                                        (const double*)X, ldx, (double*)Y, ldy, k);
-  else
-    launch(k_csr_spmm<float>, g, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const float*)A->val, (const float*)X,
-                                       ldx, (float*)Y, ldy, k);
+  // 16-byte lanes (2 FP64 or 4 FP32 columns) where k, the leading
+  // dimensions and the alignment of X and Y allow, else one value per lane.
+  // (32-byte lanes, two loads each, measured slower on the stencil.)
+  const int vec = 16 / A->sv;
+  const bool wide = k % vec == 0 && ldx % vec == 0 && ldy % vec == 0 && ((uintptr_t)X & 15) == 0 &&
+                    ((uintptr_t)Y & 15) == 0;
+  if (A->dt == SPMV_F64) {
+    if (wide) launch_spmm<double, 2>(A, X, ldx, Y, ldy, k, s);
+    else launch_spmm<double, 1>(A, X, ldx, Y, ldy, k, s);
+  } else {
+    if (wide) launch_spmm<float, 4>(A, X, ldx, Y, ldy, k, s);
+    else launch_spmm<float, 1>(A, X, ldx, Y, ldy, k, s);
+  }
   SPMV_LAUNCH_CHECK();
   return SPMV_OK;
 }

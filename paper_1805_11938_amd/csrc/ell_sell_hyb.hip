@@ -851,6 +851,7 @@ __global__ __launch_bounds__(BS) void k_coo(const int32_t* __restrict__ blk, con
     bool hd[COO_IT];
     uint64_t mk[COO_IT];
     int32_t rr[COO_IT], rp[COO_IT];
+    const bool lane0 = __lane_id() == 0;
 #pragma unroll
     for (int j = 0; j < COO_IT; ++j) {  // clamped, branch-free loads at block-uniform bases
       const int k = j * BS + t;
@@ -858,9 +859,16 @@ __global__ __launch_bounds__(BS) void k_coo(const int32_t* __restrict__ blk, con
       cc[j] = ldnt32(ccol + c0, kk);
       vv[j] = ldnt32(cval + c0, kk);
       rr[j] = ld32(crow + c0, kk);
-      rp[j] = ld32(crow + c0, kk > 0 ? kk - 1 : 0u);
+      // the previous entry's row comes from the neighbouring lane; only
+      // lane 0 (whose neighbour is in another wave) loads it
+      rp[j] = lane0 ? ld32(crow + c0, kk > 0 ? kk - 1 : 0u) : 0;
     }
     issue_fence();
+#pragma unroll
+    for (int j = 0; j < COO_IT; ++j) {
+      const int32_t up = __shfl_up(rr[j], 1, WAVE);
+      rp[j] = lane0 ? rp[j] : up;
+    }
     T xg[COO_IT];
 #pragma unroll
     for (int j = 0; j < COO_IT; ++j) xg[j] = ld32(x, (uint32_t)cc[j]);

@@ -46,6 +46,31 @@ def test_spmm_matches_oracle(torch, mi, k):
         assert rowwise_err(Ypn[:, c], Yref[:, c], den[:, c]) <= TOL[0]
 
 
+@pytest.mark.parametrize("dt", [0, 1])
+@pytest.mark.parametrize("k,ldx,ldy", [(8, 8, 8), (8, 10, 12), (6, 6, 6), (4, 4, 8), (12, 16, 12)])
+def test_spmm_wide_lanes(torch, dt, k, ldx, ldy):
+    """The 16-byte-lane SpMM (k, ldx, ldy multiples of 2 in FP64 / 4 in
+    FP32, aligned X and Y) and its fallback agree with the oracle, and the
+    columns past k are left alone."""
+    for name, A in SPMM_MATS[:2]:
+        X = synth.uniform(A.N * k, 29 + k, -1.0, 1.0).reshape(A.N, k)
+        if dt == 1:
+            X = X.astype(np.float32).astype(np.float64)
+        Yref = oracle.csr_spmm(A.M, A.ptr, A.col, A.val if dt == 0 else A.val.astype(np.float32).astype(np.float64), X)
+        val = A.val if dt == 0 else A.val.astype(np.float32)
+        Ad = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt)
+        tdt = torch.float64 if dt == 0 else torch.float32
+        Xp = torch.zeros((A.N, ldx), dtype=tdt, device="cuda")
+        Xp[:, :k] = torch.from_numpy(X).to("cuda", tdt)
+        Yp = torch.full((A.M, ldy), float("nan"), dtype=tdt, device="cuda")
+        S.check(S.lib().spmv_spmm(Ad.h, S.dptr(Xp), ldx, S.dptr(Yp), ldy, k, S.stream()))
+        Y = Yp.cpu().numpy().astype(np.float64)
+        assert np.all(np.isnan(Y[:, k:]))
+        for c in range(k):
+            den = oracle.csr_absspmv(A.M, A.ptr, A.col, A.val, X[:, c])
+            assert rowwise_err(Y[:, c], Yref[:, c], den) <= TOL[dt], (name, dt, k, c)
+
+
 def test_spmm_integer_exact(torch):
     A = synth.random_pattern(900, 700, 0.02, 7, integer_values=True)
     X = np.round(synth.uniform(700 * 8, 3, -8, 8)).reshape(700, 8)
