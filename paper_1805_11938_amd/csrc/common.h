@@ -167,12 +167,15 @@ struct spmv_mat_s {
   int4* wide = nullptr;           // (chunk, first item, item count) per split chunk
   double* part = nullptr;         // nitems * C partial sums (run scratch, split chunks only)
 
-  // HYB COO part (row-major) and its row-aligned block boundaries
-  int64_t ncoo = 0, ncoo_blk = 0;
+  // HYB COO part (row-major) and the per-tile scratch of its pass
+  int64_t ncoo = 0;
   int32_t* crow = nullptr;
   int32_t* ccol = nullptr;
   void* cval = nullptr;
-  int32_t* coo_blk = nullptr;
+  double* coo_head = nullptr;   // per COO tile: partial sum of its first row when begun earlier (run scratch)
+  double* coo_tail = nullptr;   // per COO tile: partial sum of its last row when it continues (run scratch)
+  int32_t* coo_trow = nullptr;  // per COO tile: that last row
+  int32_t* coo_tinfo = nullptr; // per COO tile: CT_TAIL / CT_SPAN / 0
 
   // CSR5
   int32_t omega = 0, c5sigma = 0;

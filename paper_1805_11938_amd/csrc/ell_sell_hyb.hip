@@ -10,10 +10,10 @@
 //   stored position to its row; y is written through it).  One thread per
 //   stored position.
 // HYB: ELL(K) + COO tail.  K from the one-third rule unless given.  The ELL
-//   kernel writes y, then the COO kernel adds the tail: COO entries are cut
-//   into blocks whose boundaries fall on row starts, so every row of the
-//   tail is finished by one workgroup (segmented reduction in LDS, carries
-//   between sub-chunks kept in the workgroup), without atomics.
+//   kernel writes y, then the COO pass adds the tail: one wave per tile of
+//   1,024 consecutive entries, a segmented scan in registers, no barrier;
+//   rows that cross tiles are finished by an ordered fix-up pass, without
+//   atomics.
 #include "common.h"
 
 namespace spmv {
@@ -777,8 +777,6 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
 }
 
 // ================================================================== HYB
-constexpr int COO_CH = 2048;  // entries per COO sub-chunk (LDS)
-constexpr int COO_IT = COO_CH / BS;
 
 __global__ void k_hyb_keys(int64_t M, const int32_t* ptr, int64_t maxlen, uint64_t* key, uint32_t* idx) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
@@ -809,122 +807,128 @@ __global__ void k_hyb_fill_coo(int64_t M, int64_t K, const int32_t* ptr, const i
   }
 }
 
-// block b processes COO entries [blk[b], blk[b+1]); boundaries on row starts
-__global__ void k_coo_blocks(int64_t ncoo, int64_t nb, const int32_t* crow, int32_t* blk) {
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nb; b += (int64_t)gridDim.x * blockDim.x) {
-    int64_t s = b * COO_CH;
-    if (b == 0) s = 0;
-    else if (b == nb || s >= ncoo) s = ncoo;
-    else if (crow[s] == crow[s - 1]) {
-      const int32_t r = crow[s];
-      int64_t lo = s, hi = ncoo;  // first entry after row r
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (crow[mid] > r) hi = mid;
-        else lo = mid + 1;
+// COO pass by wave tiles: a wave takes COO_TILE consecutive entries, lane l
+// holding entries s*64 + l (s < COO_S, coalesced), all loads and gathers in
+// flight at once and no barrier, so waves never wait on each other.  Rows are
+// reduced by a segmented scan over the lanes of each slice s, carried from
+// slice to slice; a row that ends in the tile adds its sum to y (whose value
+// was loaded with the gathers).  A row that crosses tile boundaries leaves
+// its partial sums: tail_part in the tile where it starts, head_part in each
+// later tile it reaches; k_coo_fix adds them to y in tile order.
+constexpr int COO_S = 16;
+constexpr int COO_TILE = WAVE * COO_S;
+constexpr int32_t CT_TAIL = 1;  // the tile's last row starts in it and continues into the next tile
+constexpr int32_t CT_SPAN = 2;  // one row covers the whole tile and continues on both sides
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coo_tiles(int64_t ncoo, int64_t ntiles, const int32_t* __restrict__ crow,
+                                                  const int32_t* __restrict__ ccol, const T* __restrict__ cval,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  double* __restrict__ head_part, double* __restrict__ tail_part,
+                                                  int32_t* __restrict__ tail_row, int32_t* __restrict__ tinfo) {
+  const int64_t t = (int64_t)blockIdx.x * (BS / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (t >= ntiles) return;
+  const int l = __lane_id();
+  const int64_t e0 = t * COO_TILE;
+  const int nv = (int)(ncoo - e0 < COO_TILE ? ncoo - e0 : COO_TILE);  // valid entries, >= 1
+  constexpr int32_t NONE = 0x7fffffff;  // row of the places past the last entry
+  int32_t cc[COO_S], rr[COO_S];
+  T vv[COO_S], xg[COO_S], yg[COO_S];
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s) {
+    const int k = s * WAVE + l;
+    const uint32_t kk = (uint32_t)(k < nv ? k : nv - 1);
+    cc[s] = ldnt32(ccol + e0, kk);
+    vv[s] = ldnt32(cval + e0, kk);
+    rr[s] = ld32(crow + e0, kk);
+  }
+  const int32_t rprev = t > 0 ? crow[e0 - 1] : -1;              // row before the tile
+  const int32_t rnext = nv == COO_TILE && e0 + COO_TILE < ncoo ? crow[e0 + COO_TILE] : -2;  // row after it
+  issue_fence();
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s)
+    if (s * WAVE + l >= nv) rr[s] = NONE;
+  // a place ends its row when the next entry is another row; only rows
+  // that end here and started in the tile add to y, so only they load it
+  bool en[COO_S];
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s) {  // every lane takes part in both shuffles
+    const int32_t dn = __shfl_down(rr[s], 1, WAVE);
+    const int32_t n0 = __shfl(rr[s + 1 < COO_S ? s + 1 : s], 0, WAVE);  // first row of the next slice
+    const int32_t nx = l < WAVE - 1 ? dn : (s + 1 < COO_S ? n0 : rnext);
+    en[s] = rr[s] != NONE && rr[s] != nx;
+  }
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s) xg[s] = ld32(x, (uint32_t)cc[s]);
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s) yg[s] = en[s] && rr[s] != rprev ? y[rr[s]] : (T)0;
+  issue_fence();
+  double carry = 0.0, last_v = 0.0;
+  int32_t prev_last = rprev;
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s) {
+    const int32_t r = rr[s];
+    const int32_t up = __shfl_up(r, 1, WAVE);
+    const int32_t rp = l > 0 ? up : prev_last;
+    double v = r != NONE ? (double)vv[s] * (double)xg[s] : 0.0;
+    bool f = r != rp;  // a row starts here
+    // segmented inclusive scan over the 64 lanes of this slice
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const double vn = __shfl_up(v, d, WAVE);
+      const bool fn = __shfl_up((int)f, d, WAVE) != 0;
+      if (l >= d && !f) {
+        v += vn;
+        f = fn;
       }
-      s = lo;
     }
-    blk[b] = (int32_t)s;
+    if (!f) v += carry;  // the row continues from the previous slice
+    if (en[s]) {
+      if (r == rprev) head_part[t] = v;  // the tile's first row, begun in an earlier tile
+      else y[r] = (T)((double)yg[s] + v);
+    }
+    if (s * WAVE + l == nv - 1) last_v = v;
+    carry = __shfl(v, WAVE - 1, WAVE);
+    prev_last = __shfl(r, WAVE - 1, WAVE);
+  }
+  // the last entry's row, if it continues into the next tile
+  const int ll = (nv - 1) % WAVE, sl = (nv - 1) / WAVE;
+  int32_t last_r = NONE;
+#pragma unroll
+  for (int s = 0; s < COO_S; ++s)
+    if (s == sl) last_r = __shfl(rr[s], ll, WAVE);
+  last_v = __shfl(last_v, ll, WAVE);
+  if (l == 0) {
+    int32_t info = 0;
+    if (last_r == rnext) {
+      if (last_r == rprev) {
+        head_part[t] = last_v;
+        info = CT_SPAN;
+      } else {
+        tail_part[t] = last_v;
+        tail_row[t] = last_r;
+        info = CT_TAIL;
+      }
+    }
+    tinfo[t] = info;
   }
 }
 
+// one thread per tile whose last row continues: that row's partial sums in
+// tile order, then into y
 template <typename T>
-__global__ __launch_bounds__(BS) void k_coo(const int32_t* __restrict__ blk, const int32_t* __restrict__ crow,
-                                            const int32_t* __restrict__ ccol, const T* __restrict__ cval,
-                                            const T* __restrict__ x, T* __restrict__ y) {
-  __shared__ double prod[COO_CH];
-  __shared__ int32_t hpos[COO_CH + 1];
-  __shared__ int32_t wcnt[COO_IT * (BS / WAVE)];
-  __shared__ double carry_v;
-  __shared__ int32_t carry_r;
-  const int t = threadIdx.x, w = t / WAVE;
-  const int64_t s0 = blk[blockIdx.x], e0 = blk[blockIdx.x + 1];
-  if (s0 >= e0) return;
-  if (t == 0) carry_r = -1;
-  const uint64_t lt = lanemask_lt();
-  for (int64_t c0 = s0; c0 < e0; c0 += COO_CH) {
-    const int n = (int)std::min<int64_t>(COO_CH, e0 - c0);
-    const bool last_chunk = c0 + n >= e0;
-    int32_t cc[COO_IT];
-    T vv[COO_IT];
-    bool hd[COO_IT];
-    uint64_t mk[COO_IT];
-    int32_t rr[COO_IT], rp[COO_IT];
-    const bool lane0 = __lane_id() == 0;
-#pragma unroll
-    for (int j = 0; j < COO_IT; ++j) {  // clamped, branch-free loads at block-uniform bases
-      const int k = j * BS + t;
-      const uint32_t kk = (uint32_t)(k < n ? k : n - 1);
-      cc[j] = ldnt32(ccol + c0, kk);
-      vv[j] = ldnt32(cval + c0, kk);
-      rr[j] = ld32(crow + c0, kk);
-      // the previous entry's row comes from the neighbouring lane; only
-      // lane 0 (whose neighbour is in another wave) loads it
-      rp[j] = lane0 ? ld32(crow + c0, kk > 0 ? kk - 1 : 0u) : 0;
+__global__ void k_coo_fix(int64_t ntiles, const double* __restrict__ head_part, const double* __restrict__ tail_part,
+                          const int32_t* __restrict__ tail_row, const int32_t* __restrict__ tinfo, T* __restrict__ y) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    if (tinfo[t] != CT_TAIL) continue;
+    double tot = tail_part[t];
+    int64_t u = t + 1;
+    for (;; ++u) {
+      tot += head_part[u];
+      if (tinfo[u] != CT_SPAN) break;
     }
-    issue_fence();
-#pragma unroll
-    for (int j = 0; j < COO_IT; ++j) {
-      const int32_t up = __shfl_up(rr[j], 1, WAVE);
-      rp[j] = lane0 ? rp[j] : up;
-    }
-    T xg[COO_IT];
-#pragma unroll
-    for (int j = 0; j < COO_IT; ++j) xg[j] = ld32(x, (uint32_t)cc[j]);
-    issue_fence();
-#pragma unroll
-    for (int j = 0; j < COO_IT; ++j) {
-      const int k = j * BS + t;
-      hd[j] = k < n && (k == 0 || rr[j] != rp[j]);
-      if (k < n) prod[k] = (double)vv[j] * (double)xg[j];
-      mk[j] = __ballot(hd[j]);
-      if (__lane_id() == 0) wcnt[j * (BS / WAVE) + w] = __popcll(mk[j]);
-    }
-    __syncthreads();
-    // flush a carried row that ended exactly at the previous sub-chunk
-    if (t == 0 && carry_r >= 0 && crow[c0] != carry_r) {
-      y[carry_r] = (T)((double)y[carry_r] + carry_v);
-      carry_r = -1;
-    }
-    int nh = 0;
-#pragma unroll
-    for (int j = 0; j < COO_IT; ++j) {
-      int before = nh;
-      for (int q = 0; q < w; ++q) before += wcnt[j * (BS / WAVE) + q];
-      for (int q = 0; q < BS / WAVE; ++q) nh += wcnt[j * (BS / WAVE) + q];
-      if (hd[j]) hpos[before + __popcll(mk[j] & lt)] = j * BS + t;
-    }
-    if (t == 0) hpos[nh] = n;
-    __syncthreads();
-    const int V = n / nh >= 32 ? 16 : n / nh >= 8 ? 4 : 1;
-    const int g = t / V, lane = t % V, ng = BS / V;
-    double keep_v = 0.0;
-    int32_t keep_r = -1;
-    for (int q = g; q < nh; q += ng) {
-      const int a = hpos[q], e = hpos[q + 1];
-      double sum = 0.0;
-      for (int k = a + lane; k < e; k += V) sum += prod[k];
-      sum = group_sum_rt(sum, V);
-      if (lane == 0) {
-        const int32_t r = crow[c0 + a];
-        if (q == 0 && r == carry_r) sum += carry_v;
-        if (q == nh - 1 && !last_chunk) {
-          keep_v = sum;
-          keep_r = r;
-        } else {
-          y[r] = (T)((double)y[r] + sum);
-        }
-      }
-    }
-    __syncthreads();
-    if (keep_r >= 0) {  // exactly one lane holds the open last segment
-      carry_v = keep_v;
-      carry_r = keep_r;
-    } else if (t == 0 && last_chunk) {
-      carry_r = -1;
-    }
-    __syncthreads();
+    const int32_t r = tail_row[t];
+    y[r] = (T)((double)y[r] + tot);
   }
 }
 
@@ -933,8 +937,15 @@ static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_
   if (A->M == 0) return SPMV_OK;
   SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, !(A->params.flags & SPMV_FLAG_LINEAR), s));
   if (A->ncoo > 0) {
-    launch(k_coo<T>, (unsigned)A->ncoo_blk, BS, s, A->coo_blk, A->crow, A->ccol, (const T*)A->cval, (const T*)x, (T*)y);
+    const int64_t nt = cdiv(A->ncoo, COO_TILE);
+    launch(k_coo_tiles<T>, (unsigned)cdiv(nt, BS / WAVE), BS, s, A->ncoo, nt, A->crow, A->ccol, (const T*)A->cval,
+           (const T*)x, (T*)y, A->coo_head, A->coo_tail, A->coo_trow, A->coo_tinfo);
     SPMV_LAUNCH_CHECK();
+    if (nt > 1) {
+      launch(k_coo_fix<T>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt, (const double*)A->coo_head,
+             (const double*)A->coo_tail, (const int32_t*)A->coo_trow, (const int32_t*)A->coo_tinfo, (T*)y);
+      SPMV_LAUNCH_CHECK();
+    }
   }
   return SPMV_OK;
 }
@@ -988,8 +999,6 @@ spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   SPMV_TRY(mat_alloc(A, (void**)&A->crow, sizeof(int32_t) * A->ncoo));
   SPMV_TRY(mat_alloc(A, (void**)&A->ccol, sizeof(int32_t) * A->ncoo));
   SPMV_TRY(mat_alloc(A, &A->cval, (size_t)A->sv * A->ncoo));
-  A->ncoo_blk = std::max<int64_t>(cdiv(A->ncoo, COO_CH), 1);
-  SPMV_TRY(mat_alloc(A, (void**)&A->coo_blk, sizeof(int32_t) * (A->ncoo_blk + 1)));
   if (A->ncoo) {
     const unsigned gw = (unsigned)std::min<int64_t>(cdiv(M, BS / WAVE), 1 << 20);
     if (A->dt == SPMV_F64)
@@ -1000,8 +1009,13 @@ spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
                                               A->crow, A->ccol, (float*)A->cval);
     SPMV_LAUNCH_CHECK();
   }
-  k_coo_blocks<<<grid_rows(A->ncoo_blk + 1), BS, 0, s>>>(A->ncoo, A->ncoo_blk, A->crow, A->coo_blk);
-  SPMV_LAUNCH_CHECK();
+  {  // per-tile scratch of the COO pass
+    const int64_t nt = std::max<int64_t>(cdiv(A->ncoo, COO_TILE), 1);
+    SPMV_TRY(mat_alloc(A, (void**)&A->coo_head, sizeof(double) * nt));
+    SPMV_TRY(mat_alloc(A, (void**)&A->coo_tail, sizeof(double) * nt));
+    SPMV_TRY(mat_alloc(A, (void**)&A->coo_trow, sizeof(int32_t) * nt));
+    SPMV_TRY(mat_alloc(A, (void**)&A->coo_tinfo, sizeof(int32_t) * nt));
+  }
   A->pad_slots = M * K - (src->nnz - A->ncoo);
   // ELL slots, COO (row, col, val), x once, y written once and the tail rows re-read
   A->bytes_fmt = M * K * (4 + A->sv) + A->ncoo * (8 + A->sv) + A->N * A->sv + A->M * A->sv;
