@@ -274,6 +274,29 @@ def choose(Ad: "S.Matrix", model: "S.Model"):
     return fmt, scores
 
 
+DOMAIN_TOL = 0.02  # how far (in units of each feature's training span) a feature may lie outside it
+
+
+def scaled_features(Ad: "S.Matrix", model: "S.Model") -> np.ndarray:
+    """The matrix's 12 features after the model's transform and min-max
+    scaling, on the device (spmv_scale_features): 0 and 1 are the smallest
+    and largest values among the model's training matrices."""
+    import torch
+    f = torch.tensor(Ad.features(), dtype=torch.float64, device="cuda")
+    _, lo, hi = model.params()
+    X = torch.empty(12, dtype=torch.float32, device="cuda")
+    S.check(S.lib().spmv_scale_features(S.dptr(f), 1, S.hptr(lo), S.hptr(hi), S.dptr(X), S.stream()))
+    return X.cpu().numpy().astype(np.float64)
+
+
+def in_domain(Ad: "S.Matrix", model: "S.Model", tol: float = DOMAIN_TOL) -> bool:
+    """Whether every feature lies within the range the model was trained on
+    (widened by tol of its span).  Outside it the network extrapolates, and
+    the exhaustive fallback decides instead."""
+    X = scaled_features(Ad, model)
+    return bool(np.all(X >= -tol) and np.all(X <= 1.0 + tol))
+
+
 def exhaustive(Ad, x, y):
     """The fallback and judge: profile all five formats, return the fastest."""
     times, _, params = profile_matrix(Ad, x, y)
@@ -286,10 +309,11 @@ def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB):
     converted handle with how it was chosen.
 
     With a model: predicted format, then (tune=True) the autotuner's
-    parameters for it.  Without a model, or when the model's top softmax
-    probability beats the runner-up by less than `margin`, every format is
-    profiled and the fastest is taken (the exhaustive fallback)."""
-    if model is not None:
+    parameters for it.  Without a model, when the matrix's features lie
+    outside the model's training range (in_domain), or when the model's top
+    softmax probability beats the runner-up by less than `margin`, every
+    format is profiled and the fastest is taken (the exhaustive fallback)."""
+    if model is not None and in_domain(Ad, model):
         fmt, z = choose(Ad, model)
         p = np.exp(z - z.max())
         p = np.sort(p / p.sum())[::-1]

@@ -131,6 +131,28 @@ def test_auto_uses_model_or_exhaustive_fallback(torch, trained):
     assert how3 == "exhaustive"
 
 
+def test_auto_falls_back_outside_the_training_range(torch, trained, records):
+    """A matrix smaller than every training matrix (4,096 rows; the set has
+    10^4..2x10^6) is decided by exhaustive profiling, a training-range matrix
+    by the model; the scaled features agree with the host transform."""
+    (models, test) = trained
+    model, _ = models["f64"]
+    A = synth.laplace2d(64)
+    Ad = S.Matrix.from_host(A)
+    assert not SEL.in_domain(Ad, model)
+    x = device_vec(synth.vector(A.N, 3), 0)
+    y = torch.empty(A.M, dtype=torch.float64, device="cuda")
+    B, fmt, how = SEL.auto(Ad, x, y, model, scrub=16 << 20)
+    assert how == "exhaustive" and B.fmt == fmt
+    r = next(r for r in records if r["index"] in test and r["dtype"] == "f64")
+    H = SEL._to_device(synth.make(synth.selector_spec(r["index"])), S.F64)
+    X = SEL.scaled_features(H, model)
+    _, lo, hi = model.params()
+    Xh, _, _ = SEL.host_scale(np.array([H.features()]), lo, hi)
+    assert np.allclose(X, Xh[0], rtol=0, atol=1e-5)
+    assert SEL.in_domain(H, model) == bool(np.all(Xh >= -SEL.DOMAIN_TOL) and np.all(Xh <= 1 + SEL.DOMAIN_TOL))
+
+
 def test_auto_for_calls_keeps_csr_for_few_calls(torch, trained):
     (models, _) = trained
     model, _ = models["f64"]
