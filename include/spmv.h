@@ -88,6 +88,9 @@ typedef struct {
                                     32 wide use the one-pass narrow kernel) */
 #define SPMV_FLAG_CSR_BANDS 16u /* CSR: split the columns into 8 bands, one per XCD, so each XCD's L2 holds its
                                    eighth of x; per-band partial sums are added by a second pass */
+#define SPMV_FLAG_CSR_TILES 32u /* CSR: one wave per tile of 1,024 consecutive nonzeros (segmented scan in
+                                   registers, no workgroup barrier), rows crossing tiles finished by an ordered
+                                   fix-up pass; for irregular rows.  Ignored with csr_lanes_per_row > 0 or bands */
 
 typedef struct {
   int32_t fmt, dtype;

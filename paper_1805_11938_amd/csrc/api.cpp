@@ -162,6 +162,7 @@ spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* 
         SPMV_HIP(hipMemcpyAsync(A->val, csr->val, (size_t)A->sv * A->nnz, hipMemcpyDeviceToDevice, st));
         SPMV_TRY(csr_build_blocks(A, st));
         A->bytes_fmt = bytes_min(A);
+        if ((A->params.flags & SPMV_FLAG_CSR_TILES) && V == 0) SPMV_TRY(csr_build_tiles(A, st));
         if (A->params.flags & SPMV_FLAG_CSR_BANDS) {
           SPMV_TRY(csr_build_bands(A, st));
           A->bytes_fmt += (int64_t)(A->nbands - 1) * 4 * (A->M + 1);  // one row pointer per band

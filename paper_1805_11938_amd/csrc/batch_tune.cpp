@@ -160,13 +160,17 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
     case SPMV_FMT_CSR:
       add([](spmv_params_t& p) {
         p.csr_lanes_per_row = 0;
-        p.flags &= ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR | SPMV_FLAG_CSR_BANDS);
+        p.flags &= ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR | SPMV_FLAG_CSR_BANDS | SPMV_FLAG_CSR_TILES);
       });
       add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags |= SPMV_FLAG_CSR_WAVES; });
       add([](spmv_params_t& p) { p.csr_lanes_per_row = 0; p.flags = (p.flags & ~SPMV_FLAG_CSR_WAVES) | SPMV_FLAG_LINEAR; });
       add([](spmv_params_t& p) {
         p.csr_lanes_per_row = 0;
         p.flags = (p.flags & ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR)) | SPMV_FLAG_CSR_BANDS;
+      });
+      add([](spmv_params_t& p) {
+        p.csr_lanes_per_row = 0;
+        p.flags = (p.flags & ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR | SPMV_FLAG_CSR_BANDS)) | SPMV_FLAG_CSR_TILES;
       });
       for (int V : {4, 8, 16, 32}) add([V](spmv_params_t& p) { p.csr_lanes_per_row = V; });
       break;

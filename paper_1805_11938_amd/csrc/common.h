@@ -130,6 +130,13 @@ struct spmv_mat_s {
   int64_t nblk = 0;
   int32_t* unit_row = nullptr; // CSR wave units: unit u owns rows [unit_row[u], unit_row[u+1])
   int64_t nunits = 0;
+  int64_t ntiles_csr = 0;      // CSR wave tiles (SPMV_FLAG_CSR_TILES): tiles of TILE_E nonzeros
+  int32_t* ct_start = nullptr;  // ntiles+1: first row starting at or after the tile's first entry (M at the end)
+  int32_t* ct_cont = nullptr;   // ntiles+1: row holding the tile's first entry
+  double* ct_head = nullptr;    // per tile: run scratch of the tile reduction (as the HYB COO pass)
+  double* ct_tail = nullptr;
+  int32_t* ct_trow = nullptr;
+  int32_t* ct_info = nullptr;
   int64_t nseg = 0, nlong = 0; // CSR long rows cut into segments
   int2* segs = nullptr;        // (row, first nonzero) per segment
   int4* longs = nullptr;       // (row, first segment, segment count) per long row
@@ -236,6 +243,7 @@ spmv_status_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 // ------------------------------------------------------------- builders
 spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s);
 spmv_status_t csr_build_bands(spmv_mat_s* A, hipStream_t s);
+spmv_status_t csr_build_tiles(spmv_mat_s* A, hipStream_t s);
 // Splits src's entries by column band (band b: col in [b*bw, (b+1)*bw)) into
 // nb CSRs of all M rows: bptr is nb x (M+1), each relative to its band's first
 // entry off[b]; bcol / bval hold the bands one after another.
@@ -349,6 +357,116 @@ __device__ __forceinline__ double row_dot(const int32_t* __restrict__ col, const
   }
   for (; k < e; k += stride) s0 += (double)ldnt(val + k) * (double)x[ldnt(col + k)];
   return (s0 + s1) + (s2 + s3);
+}
+
+// ------------------------------------------------- wave tiles of entries
+// A wave reduces TILE_S * 64 consecutive entries in row order (lane l holds
+// entries s*64 + l, s < TILE_S): the caller has loaded, for each place, the
+// column, the value and the row (TILE_NONE past the last entry), and passes
+// the row that continues into the tile from before (rprev, else -1) and the
+// row that continues after it (rnext, else -2).  Rows are reduced by a
+// segmented scan over the lanes of each slice, carried from slice to slice.
+// A row that ends in the tile and began in it is written to y (added to the
+// value y holds when ADD, whose load goes out with the gathers); a row
+// crossing tile boundaries leaves tail_part in the tile where it starts and
+// head_part in each later tile it reaches, and k_tile_fix finishes it.
+constexpr int TILE_S = 16;
+constexpr int TILE_E = WAVE * TILE_S;
+constexpr int32_t TILE_NONE = 0x7fffffff;
+constexpr int32_t TILE_TAIL = 1;  // the tile's last row starts in it and continues into the next tile
+constexpr int32_t TILE_SPAN = 2;  // one row covers the whole tile and continues on both sides
+
+template <typename T, bool ADD>
+__device__ __forceinline__ void wave_tile_reduce(int64_t t, int nv, const int32_t (&rr)[TILE_S],
+                                                 const int32_t (&cc)[TILE_S], const T (&vv)[TILE_S],
+                                                 int32_t rprev, int32_t rnext, const T* __restrict__ x,
+                                                 T* __restrict__ y, double* __restrict__ head_part,
+                                                 double* __restrict__ tail_part, int32_t* __restrict__ tail_row,
+                                                 int32_t* __restrict__ tinfo) {
+  const int l = __lane_id();
+  // a place ends its row when the next entry is another row
+  bool en[TILE_S];
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s) {  // every lane takes part in both shuffles
+    const int32_t dn = __shfl_down(rr[s], 1, WAVE);
+    const int32_t n0 = __shfl(rr[s + 1 < TILE_S ? s + 1 : s], 0, WAVE);  // first row of the next slice
+    const int32_t nx = l < WAVE - 1 ? dn : (s + 1 < TILE_S ? n0 : rnext);
+    en[s] = rr[s] != TILE_NONE && rr[s] != nx;
+  }
+  T xg[TILE_S], yg[TILE_S];
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s) xg[s] = ld32(x, (uint32_t)cc[s]);
+  if (ADD) {
+#pragma unroll
+    for (int s = 0; s < TILE_S; ++s) yg[s] = en[s] && rr[s] != rprev ? y[rr[s]] : (T)0;
+  }
+  issue_fence();
+  double carry = 0.0, last_v = 0.0;
+  int32_t prev_last = rprev;
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s) {
+    const int32_t r = rr[s];
+    const int32_t up = __shfl_up(r, 1, WAVE);
+    const int32_t rp = l > 0 ? up : prev_last;
+    double v = r != TILE_NONE ? (double)vv[s] * (double)xg[s] : 0.0;
+    bool f = r != rp;  // a row starts here
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {  // segmented inclusive scan over the slice
+      const double vn = __shfl_up(v, d, WAVE);
+      const bool fn = __shfl_up((int)f, d, WAVE) != 0;
+      if (l >= d && !f) {
+        v += vn;
+        f = fn;
+      }
+    }
+    if (!f) v += carry;  // the row continues from the previous slice
+    if (en[s]) {
+      if (r == rprev) head_part[t] = v;  // the tile's first row, begun in an earlier tile
+      else y[r] = ADD ? (T)((double)yg[s] + v) : (T)v;
+    }
+    if (s * WAVE + l == nv - 1) last_v = v;
+    carry = __shfl(v, WAVE - 1, WAVE);
+    prev_last = __shfl(r, WAVE - 1, WAVE);
+  }
+  // the last entry's row, if it continues into the next tile
+  const int ll = (nv - 1) % WAVE, sl = (nv - 1) / WAVE;
+  int32_t last_r = TILE_NONE;
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s)
+    if (s == sl) last_r = __shfl(rr[s], ll, WAVE);
+  last_v = __shfl(last_v, ll, WAVE);
+  if (l == 0) {
+    int32_t info = 0;
+    if (last_r == rnext) {
+      if (last_r == rprev) {
+        head_part[t] = last_v;
+        info = TILE_SPAN;
+      } else {
+        tail_part[t] = last_v;
+        tail_row[t] = last_r;
+        info = TILE_TAIL;
+      }
+    }
+    tinfo[t] = info;
+  }
+}
+
+// one thread per tile whose last row continues: the row's partial sums in
+// tile order, then into y (added to it when ADD)
+template <typename T, bool ADD>
+__global__ void k_tile_fix(int64_t ntiles, const double* __restrict__ head_part, const double* __restrict__ tail_part,
+                           const int32_t* __restrict__ tail_row, const int32_t* __restrict__ tinfo,
+                           T* __restrict__ y) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    if (tinfo[t] != TILE_TAIL) continue;
+    double tot = tail_part[t];
+    for (int64_t u = t + 1;; ++u) {
+      tot += head_part[u];
+      if (tinfo[u] != TILE_SPAN) break;
+    }
+    const int32_t r = tail_row[t];
+    y[r] = ADD ? (T)((double)y[r] + tot) : (T)tot;
+  }
 }
 
 }  // namespace spmv

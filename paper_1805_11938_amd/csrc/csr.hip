@@ -435,9 +435,9 @@ constexpr int WIT = WCAP / WAVE;
 constexpr int WRCAP = WU;           // row pointers a wave stages in LDS (a unit never has more rows)
 
 __device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 __device__ __forceinline__ int wave_lanes_for(int64_t nz, int64_t rows) {
@@ -559,6 +559,114 @@ __global__ __launch_bounds__(BS) void k_csr_vector(int64_t M, const int32_t* __r
   if (lane == 0) y[r] = (T)s;
 }
 
+// ------------------------------------------------------------ wave tiles
+// SPMV_FLAG_CSR_TILES: a wave takes TILE_E consecutive nonzeros (the same
+// reduction as HYB's COO pass, wave_tile_reduce), with no barrier and every
+// load in flight.  CSR stores no row per entry, so the wave marks where the
+// rows starting in its tile begin (a per-wave LDS table: row id at its first
+// entry's place, -1 elsewhere) and a running maximum over the places gives
+// every entry its row (rows increase along the tile).  Empty rows starting
+// in the tile are written as 0.  Per tile, conversion stores tstart (first
+// row whose first entry is at or after the tile's first entry; M past the
+// end) and tcont (row holding the tile's first entry).
+__global__ void k_csr_tile_rows(int64_t M, int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
+                                int32_t* __restrict__ tstart, int32_t* __restrict__ tcont) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    if (t == ntiles) {
+      tstart[t] = (int32_t)M;
+      tcont[t] = (int32_t)M;
+      continue;
+    }
+    const int64_t e0 = t * TILE_E;
+    int64_t lo = 0, hi = M;  // first r with ptr[r] >= e0
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ptr[mid] >= e0) hi = mid;
+      else lo = mid + 1;
+    }
+    tstart[t] = (int32_t)lo;
+    lo = 0, hi = M;  // first r with ptr[r] > e0; the row holding entry e0 is the one before
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ptr[mid] > e0) hi = mid;
+      else lo = mid + 1;
+    }
+    tcont[t] = (int32_t)(lo - 1);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                  const int32_t* __restrict__ tstart, const int32_t* __restrict__ tcont,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  double* __restrict__ head_part, double* __restrict__ tail_part,
+                                                  int32_t* __restrict__ tail_row, int32_t* __restrict__ tinfo) {
+  __shared__ int32_t rid[BS / WAVE][TILE_E];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int64_t t = (int64_t)blockIdx.x * (BS / WAVE) + w;
+  if (t >= ntiles) return;
+  const int l = __lane_id();
+  const int64_t e0 = t * TILE_E;
+  const int nv = (int)(nnz - e0 < TILE_E ? nnz - e0 : TILE_E);  // entries in the tile, >= 1
+  int32_t* rw = rid[w];
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s) rw[s * WAVE + l] = -1;
+  const int32_t r0 = tstart[t], r1 = tstart[t + 1], rc = tcont[t];
+  const int32_t rprev = ptr[rc] < e0 ? rc : -1;  // the row holding the first entry began earlier
+  const int32_t rn = tcont[t + 1];
+  const int32_t rnext = t + 1 < ntiles && ptr[rn] < e0 + TILE_E ? rn : -2;  // the last row continues after
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int64_t r = r0 + l; r < r1; r += WAVE) {  // rows starting in the tile
+    const int32_t a = ptr[r], b = ptr[r + 1];
+    if (b > a) rw[a - e0] = (int32_t)r;
+    else y[r] = (T)0;
+  }
+  int32_t cc[TILE_S], rr[TILE_S];
+  T vv[TILE_S];
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s) {
+    const int k = s * WAVE + l;
+    const uint32_t kk = (uint32_t)(k < nv ? k : nv - 1);
+    cc[s] = ldnt32(col + e0, kk);
+    vv[s] = ldnt32(val + e0, kk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  int32_t run = rc;  // row of the entries before the first mark
+#pragma unroll
+  for (int s = 0; s < TILE_S; ++s) {
+    int32_t v = rw[s * WAVE + l];
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {  // inclusive running maximum over the slice
+      const int32_t u = __shfl_up(v, d, WAVE);
+      if (l >= d) v = u > v ? u : v;
+    }
+    v = run > v ? run : v;
+    run = __shfl(v, WAVE - 1, WAVE);
+    rr[s] = s * WAVE + l < nv ? v : TILE_NONE;
+  }
+  issue_fence();
+  wave_tile_reduce<T, false>(t, nv, rr, cc, vv, rprev, rnext, x, y, head_part, tail_part, tail_row, tinfo);
+}
+
+spmv_status_t csr_build_tiles(spmv_mat_s* A, hipStream_t s) {
+  A->ntiles_csr = cdiv(A->nnz, TILE_E);
+  if (A->ntiles_csr == 0) return SPMV_OK;  // no entries: the row-block kernel writes the zeros
+  const int64_t nt = A->ntiles_csr;
+  SPMV_TRY(mat_alloc(A, (void**)&A->ct_start, sizeof(int32_t) * (nt + 1)));
+  SPMV_TRY(mat_alloc(A, (void**)&A->ct_cont, sizeof(int32_t) * (nt + 1)));
+  SPMV_TRY(mat_alloc(A, (void**)&A->ct_head, sizeof(double) * nt));
+  SPMV_TRY(mat_alloc(A, (void**)&A->ct_tail, sizeof(double) * nt));
+  SPMV_TRY(mat_alloc(A, (void**)&A->ct_trow, sizeof(int32_t) * nt));
+  SPMV_TRY(mat_alloc(A, (void**)&A->ct_info, sizeof(int32_t) * nt));
+  k_csr_tile_rows<<<(unsigned)std::min<int64_t>(cdiv(nt + 1, BS), 65536), BS, 0, s>>>(A->M, A->nnz, nt, A->ptr,
+                                                                                     A->ct_start, A->ct_cont);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
+}
+
 template <typename T>
 static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   if (A->M == 0) return SPMV_OK;
@@ -566,6 +674,18 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   const int32_t* ptr = A->ptr;
   const T* val = (const T*)A->val;
   if (V == 0 && A->nbands > 0) return run_csr_bands<T>(A, x, y, s);
+  if (V == 0 && A->ntiles_csr > 0) {
+    const int64_t nt = A->ntiles_csr;
+    launch(k_csr_tiles<T>, (unsigned)cdiv(nt, BS / WAVE), BS, s, A->nnz, nt, ptr, A->col, val, A->ct_start, A->ct_cont,
+           x, y, A->ct_head, A->ct_tail, A->ct_trow, A->ct_info);
+    SPMV_LAUNCH_CHECK();
+    if (nt > 1)
+      launch(k_tile_fix<T, false>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt,
+             (const double*)A->ct_head, (const double*)A->ct_tail, (const int32_t*)A->ct_trow,
+             (const int32_t*)A->ct_info, y);
+    SPMV_LAUNCH_CHECK();
+    return SPMV_OK;
+  }
   if (V == 0) {
     if (!(A->params.flags & SPMV_FLAG_CSR_WAVES)) {
       if (A->params.flags & SPMV_FLAG_LINEAR)

@@ -807,19 +807,9 @@ __global__ void k_hyb_fill_coo(int64_t M, int64_t K, const int32_t* ptr, const i
   }
 }
 
-// COO pass by wave tiles: a wave takes COO_TILE consecutive entries, lane l
-// holding entries s*64 + l (s < COO_S, coalesced), all loads and gathers in
-// flight at once and no barrier, so waves never wait on each other.  Rows are
-// reduced by a segmented scan over the lanes of each slice s, carried from
-// slice to slice; a row that ends in the tile adds its sum to y (whose value
-// was loaded with the gathers).  A row that crosses tile boundaries leaves
-// its partial sums: tail_part in the tile where it starts, head_part in each
-// later tile it reaches; k_coo_fix adds them to y in tile order.
-constexpr int COO_S = 16;
-constexpr int COO_TILE = WAVE * COO_S;
-constexpr int32_t CT_TAIL = 1;  // the tile's last row starts in it and continues into the next tile
-constexpr int32_t CT_SPAN = 2;  // one row covers the whole tile and continues on both sides
-
+// COO pass by wave tiles (wave_tile_reduce): a wave takes TILE_E
+// consecutive tail entries with all loads and gathers in flight and no
+// barrier; the tail's rows are added to the y the ELL kernel wrote.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_coo_tiles(int64_t ncoo, int64_t ntiles, const int32_t* __restrict__ crow,
                                                   const int32_t* __restrict__ ccol, const T* __restrict__ cval,
@@ -829,107 +819,25 @@ __global__ __launch_bounds__(BS) void k_coo_tiles(int64_t ncoo, int64_t ntiles, 
   const int64_t t = (int64_t)blockIdx.x * (BS / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   if (t >= ntiles) return;
   const int l = __lane_id();
-  const int64_t e0 = t * COO_TILE;
-  const int nv = (int)(ncoo - e0 < COO_TILE ? ncoo - e0 : COO_TILE);  // valid entries, >= 1
-  constexpr int32_t NONE = 0x7fffffff;  // row of the places past the last entry
-  int32_t cc[COO_S], rr[COO_S];
-  T vv[COO_S], xg[COO_S], yg[COO_S];
+  const int64_t e0 = t * TILE_E;
+  const int nv = (int)(ncoo - e0 < TILE_E ? ncoo - e0 : TILE_E);  // valid entries, >= 1
+  int32_t cc[TILE_S], rr[TILE_S];
+  T vv[TILE_S];
 #pragma unroll
-  for (int s = 0; s < COO_S; ++s) {
+  for (int s = 0; s < TILE_S; ++s) {
     const int k = s * WAVE + l;
     const uint32_t kk = (uint32_t)(k < nv ? k : nv - 1);
     cc[s] = ldnt32(ccol + e0, kk);
     vv[s] = ldnt32(cval + e0, kk);
     rr[s] = ld32(crow + e0, kk);
   }
-  const int32_t rprev = t > 0 ? crow[e0 - 1] : -1;              // row before the tile
-  const int32_t rnext = nv == COO_TILE && e0 + COO_TILE < ncoo ? crow[e0 + COO_TILE] : -2;  // row after it
+  const int32_t rprev = t > 0 ? crow[e0 - 1] : -1;                                          // row before the tile
+  const int32_t rnext = nv == TILE_E && e0 + TILE_E < ncoo ? crow[e0 + TILE_E] : -2;  // row after it
   issue_fence();
 #pragma unroll
-  for (int s = 0; s < COO_S; ++s)
-    if (s * WAVE + l >= nv) rr[s] = NONE;
-  // a place ends its row when the next entry is another row; only rows
-  // that end here and started in the tile add to y, so only they load it
-  bool en[COO_S];
-#pragma unroll
-  for (int s = 0; s < COO_S; ++s) {  // every lane takes part in both shuffles
-    const int32_t dn = __shfl_down(rr[s], 1, WAVE);
-    const int32_t n0 = __shfl(rr[s + 1 < COO_S ? s + 1 : s], 0, WAVE);  // first row of the next slice
-    const int32_t nx = l < WAVE - 1 ? dn : (s + 1 < COO_S ? n0 : rnext);
-    en[s] = rr[s] != NONE && rr[s] != nx;
-  }
-#pragma unroll
-  for (int s = 0; s < COO_S; ++s) xg[s] = ld32(x, (uint32_t)cc[s]);
-#pragma unroll
-  for (int s = 0; s < COO_S; ++s) yg[s] = en[s] && rr[s] != rprev ? y[rr[s]] : (T)0;
-  issue_fence();
-  double carry = 0.0, last_v = 0.0;
-  int32_t prev_last = rprev;
-#pragma unroll
-  for (int s = 0; s < COO_S; ++s) {
-    const int32_t r = rr[s];
-    const int32_t up = __shfl_up(r, 1, WAVE);
-    const int32_t rp = l > 0 ? up : prev_last;
-    double v = r != NONE ? (double)vv[s] * (double)xg[s] : 0.0;
-    bool f = r != rp;  // a row starts here
-    // segmented inclusive scan over the 64 lanes of this slice
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const double vn = __shfl_up(v, d, WAVE);
-      const bool fn = __shfl_up((int)f, d, WAVE) != 0;
-      if (l >= d && !f) {
-        v += vn;
-        f = fn;
-      }
-    }
-    if (!f) v += carry;  // the row continues from the previous slice
-    if (en[s]) {
-      if (r == rprev) head_part[t] = v;  // the tile's first row, begun in an earlier tile
-      else y[r] = (T)((double)yg[s] + v);
-    }
-    if (s * WAVE + l == nv - 1) last_v = v;
-    carry = __shfl(v, WAVE - 1, WAVE);
-    prev_last = __shfl(r, WAVE - 1, WAVE);
-  }
-  // the last entry's row, if it continues into the next tile
-  const int ll = (nv - 1) % WAVE, sl = (nv - 1) / WAVE;
-  int32_t last_r = NONE;
-#pragma unroll
-  for (int s = 0; s < COO_S; ++s)
-    if (s == sl) last_r = __shfl(rr[s], ll, WAVE);
-  last_v = __shfl(last_v, ll, WAVE);
-  if (l == 0) {
-    int32_t info = 0;
-    if (last_r == rnext) {
-      if (last_r == rprev) {
-        head_part[t] = last_v;
-        info = CT_SPAN;
-      } else {
-        tail_part[t] = last_v;
-        tail_row[t] = last_r;
-        info = CT_TAIL;
-      }
-    }
-    tinfo[t] = info;
-  }
-}
-
-// one thread per tile whose last row continues: that row's partial sums in
-// tile order, then into y
-template <typename T>
-__global__ void k_coo_fix(int64_t ntiles, const double* __restrict__ head_part, const double* __restrict__ tail_part,
-                          const int32_t* __restrict__ tail_row, const int32_t* __restrict__ tinfo, T* __restrict__ y) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
-    if (tinfo[t] != CT_TAIL) continue;
-    double tot = tail_part[t];
-    int64_t u = t + 1;
-    for (;; ++u) {
-      tot += head_part[u];
-      if (tinfo[u] != CT_SPAN) break;
-    }
-    const int32_t r = tail_row[t];
-    y[r] = (T)((double)y[r] + tot);
-  }
+  for (int s = 0; s < TILE_S; ++s)
+    if (s * WAVE + l >= nv) rr[s] = TILE_NONE;
+  wave_tile_reduce<T, true>(t, nv, rr, cc, vv, rprev, rnext, x, y, head_part, tail_part, tail_row, tinfo);
 }
 
 template <typename T>
@@ -937,13 +845,14 @@ static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_
   if (A->M == 0) return SPMV_OK;
   SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, !(A->params.flags & SPMV_FLAG_LINEAR), s));
   if (A->ncoo > 0) {
-    const int64_t nt = cdiv(A->ncoo, COO_TILE);
+    const int64_t nt = cdiv(A->ncoo, TILE_E);
     launch(k_coo_tiles<T>, (unsigned)cdiv(nt, BS / WAVE), BS, s, A->ncoo, nt, A->crow, A->ccol, (const T*)A->cval,
            (const T*)x, (T*)y, A->coo_head, A->coo_tail, A->coo_trow, A->coo_tinfo);
     SPMV_LAUNCH_CHECK();
     if (nt > 1) {
-      launch(k_coo_fix<T>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt, (const double*)A->coo_head,
-             (const double*)A->coo_tail, (const int32_t*)A->coo_trow, (const int32_t*)A->coo_tinfo, (T*)y);
+      launch(k_tile_fix<T, true>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt,
+             (const double*)A->coo_head, (const double*)A->coo_tail, (const int32_t*)A->coo_trow,
+             (const int32_t*)A->coo_tinfo, (T*)y);
       SPMV_LAUNCH_CHECK();
     }
   }
@@ -1010,7 +919,7 @@ spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     SPMV_LAUNCH_CHECK();
   }
   {  // per-tile scratch of the COO pass
-    const int64_t nt = std::max<int64_t>(cdiv(A->ncoo, COO_TILE), 1);
+    const int64_t nt = std::max<int64_t>(cdiv(A->ncoo, TILE_E), 1);
     SPMV_TRY(mat_alloc(A, (void**)&A->coo_head, sizeof(double) * nt));
     SPMV_TRY(mat_alloc(A, (void**)&A->coo_tail, sizeof(double) * nt));
     SPMV_TRY(mat_alloc(A, (void**)&A->coo_trow, sizeof(int32_t) * nt));

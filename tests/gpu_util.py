@@ -43,6 +43,7 @@ FORMAT_CONFIGS = [
     ("csr", {"flags": 2}),
     ("csr", {"flags": 4}),
     ("csr", {"flags": 16}),
+    ("csr", {"flags": 32}),
     ("csr5", {}),
     ("csr5", {"csr5_sigma": 4}),
     ("csr5", {"csr5_sigma": 32}),
