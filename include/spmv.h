@@ -220,7 +220,8 @@ spmv_status_t spmv_copy_probe(int64_t bytes, int reps, spmv_stream_t s, double* 
 spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int reps, int64_t scrub_bytes,
                                 spmv_stream_t s, double* ms);
 
-/* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: V;
+/* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: row
+ * blocks, wave units, linear order, XCD bands, wave tiles, V lanes per row;
  * HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma; SELL sigma in
  * {1, C, 8C, 256C, M}, M being one window over all rows, and, when x exceeds
  * 8 MiB, column bands of at most 8 MiB of x with sigma = M; CSR5: also such

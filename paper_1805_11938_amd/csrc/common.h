@@ -370,6 +370,66 @@ __device__ __forceinline__ double row_dot(const int32_t* __restrict__ col, const
 // value y holds when ADD, whose load goes out with the gathers); a row
 // crossing tile boundaries leaves tail_part in the tile where it starts and
 // head_part in each later tile it reaches, and k_tile_fix finishes it.
+// Cross-lane steps of the tile reduction, as DPP moves (ALU, no LDS round
+// trip): within-row shifts (row_shr:d), the row broadcasts of lanes 15 and
+// 31 that carry a scan across the four 16-lane rows, and whole-wave shifts
+// by one lane.  A lane with no source (or in a row the mask leaves out)
+// reads `old`.
+enum : int { DPP_ROW_SR1 = 0x111, DPP_ROW_SR2 = 0x112, DPP_ROW_SR4 = 0x114, DPP_ROW_SR8 = 0x118,
+             DPP_WF_SL1 = 0x130, DPP_WF_SR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143 };
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int32_t dpp_i(int32_t v, int32_t old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {  // old = +0.0
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)(uint32_t)b, CTRL, ROWS, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)(uint32_t)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// one step of a segmented inclusive scan: add the source's partial unless a
+// row already started at or before this lane within the window
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(double& v, int32_t& f) {
+  const double vn = dpp_d<CTRL, ROWS>(v);
+  const int32_t fn = dpp_i<CTRL, ROWS>(f, 0);
+  if (!f) {
+    v += vn;
+    f = fn;
+  }
+}
+// segmented inclusive scan of v over the 64 lanes, f = 1 where a row starts;
+// returns with f = 1 where a row started at or before the lane
+__device__ __forceinline__ void seg_scan64(double& v, int32_t& f) {
+  seg_step<DPP_ROW_SR1, 0xf>(v, f);
+  seg_step<DPP_ROW_SR2, 0xf>(v, f);
+  seg_step<DPP_ROW_SR4, 0xf>(v, f);
+  seg_step<DPP_ROW_SR8, 0xf>(v, f);
+  seg_step<DPP_ROW_BCAST15, 0xa>(v, f);
+  seg_step<DPP_ROW_BCAST31, 0xc>(v, f);
+}
+// inclusive running maximum over the 64 lanes (values >= -1)
+__device__ __forceinline__ int32_t max_scan64(int32_t v) {
+  constexpr int32_t LOW = -2147483647 - 1;
+  int32_t u;
+  u = dpp_i<DPP_ROW_SR1, 0xf>(v, LOW); v = u > v ? u : v;
+  u = dpp_i<DPP_ROW_SR2, 0xf>(v, LOW); v = u > v ? u : v;
+  u = dpp_i<DPP_ROW_SR4, 0xf>(v, LOW); v = u > v ? u : v;
+  u = dpp_i<DPP_ROW_SR8, 0xf>(v, LOW); v = u > v ? u : v;
+  u = dpp_i<DPP_ROW_BCAST15, 0xa>(v, LOW); v = u > v ? u : v;
+  u = dpp_i<DPP_ROW_BCAST31, 0xc>(v, LOW); v = u > v ? u : v;
+  return v;
+}
+
 constexpr int TILE_S = 16;
 constexpr int TILE_E = WAVE * TILE_S;
 constexpr int32_t TILE_NONE = 0x7fffffff;
@@ -387,9 +447,9 @@ __device__ __forceinline__ void wave_tile_reduce(int64_t t, int nv, const int32_
   // a place ends its row when the next entry is another row
   bool en[TILE_S];
 #pragma unroll
-  for (int s = 0; s < TILE_S; ++s) {  // every lane takes part in both shuffles
-    const int32_t dn = __shfl_down(rr[s], 1, WAVE);
-    const int32_t n0 = __shfl(rr[s + 1 < TILE_S ? s + 1 : s], 0, WAVE);  // first row of the next slice
+  for (int s = 0; s < TILE_S; ++s) {
+    const int32_t dn = dpp_i<DPP_WF_SL1, 0xf>(rr[s], 0);  // lane l + 1's row (lane 63: none)
+    const int32_t n0 = __builtin_amdgcn_readlane(rr[s + 1 < TILE_S ? s + 1 : s], 0);  // next slice's first row
     const int32_t nx = l < WAVE - 1 ? dn : (s + 1 < TILE_S ? n0 : rnext);
     en[s] = rr[s] != TILE_NONE && rr[s] != nx;
   }
@@ -406,35 +466,27 @@ __device__ __forceinline__ void wave_tile_reduce(int64_t t, int nv, const int32_
 #pragma unroll
   for (int s = 0; s < TILE_S; ++s) {
     const int32_t r = rr[s];
-    const int32_t up = __shfl_up(r, 1, WAVE);
+    const int32_t up = dpp_i<DPP_WF_SR1, 0xf>(r, 0);  // lane l - 1's row (lane 0: none)
     const int32_t rp = l > 0 ? up : prev_last;
     double v = r != TILE_NONE ? (double)vv[s] * (double)xg[s] : 0.0;
-    bool f = r != rp;  // a row starts here
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {  // segmented inclusive scan over the slice
-      const double vn = __shfl_up(v, d, WAVE);
-      const bool fn = __shfl_up((int)f, d, WAVE) != 0;
-      if (l >= d && !f) {
-        v += vn;
-        f = fn;
-      }
-    }
-    if (!f) v += carry;  // the row continues from the previous slice
+    int32_t f = r != rp;  // a row starts here
+    seg_scan64(v, f);     // segmented inclusive scan over the slice
+    if (!f) v += carry;   // the row continues from the previous slice
     if (en[s]) {
       if (r == rprev) head_part[t] = v;  // the tile's first row, begun in an earlier tile
       else y[r] = ADD ? (T)((double)yg[s] + v) : (T)v;
     }
     if (s * WAVE + l == nv - 1) last_v = v;
-    carry = __shfl(v, WAVE - 1, WAVE);
-    prev_last = __shfl(r, WAVE - 1, WAVE);
+    carry = readlane_d(v, WAVE - 1);
+    prev_last = __builtin_amdgcn_readlane(r, WAVE - 1);
   }
   // the last entry's row, if it continues into the next tile
-  const int ll = (nv - 1) % WAVE, sl = (nv - 1) / WAVE;
+  const int ll = __builtin_amdgcn_readfirstlane((nv - 1) % WAVE), sl = (nv - 1) / WAVE;
   int32_t last_r = TILE_NONE;
 #pragma unroll
   for (int s = 0; s < TILE_S; ++s)
-    if (s == sl) last_r = __shfl(rr[s], ll, WAVE);
-  last_v = __shfl(last_v, ll, WAVE);
+    if (s == sl) last_r = __builtin_amdgcn_readlane(rr[s], ll);
+  last_v = readlane_d(last_v, ll);
   if (l == 0) {
     int32_t info = 0;
     if (last_r == rnext) {

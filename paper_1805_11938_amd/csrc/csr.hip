@@ -637,14 +637,9 @@ __global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, c
   int32_t run = rc;  // row of the entries before the first mark
 #pragma unroll
   for (int s = 0; s < TILE_S; ++s) {
-    int32_t v = rw[s * WAVE + l];
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {  // inclusive running maximum over the slice
-      const int32_t u = __shfl_up(v, d, WAVE);
-      if (l >= d) v = u > v ? u : v;
-    }
+    int32_t v = max_scan64(rw[s * WAVE + l]);  // inclusive running maximum over the slice
     v = run > v ? run : v;
-    run = __shfl(v, WAVE - 1, WAVE);
+    run = __builtin_amdgcn_readlane(v, WAVE - 1);
     rr[s] = s * WAVE + l < nv ? v : TILE_NONE;
   }
   issue_fence();
