@@ -73,11 +73,11 @@ typedef struct {
   int32_t csr5_sigma;        /* tile height 1..32; default 16 */
   int64_t max_bytes;         /* byte cap of the converted format; 0 = default (SPMV_MAX_BYTES env or 64 GiB) */
   uint32_t flags;            /* SPMV_FLAG_* */
-  int32_t bands;             /* SELL and CSR5: split the columns into this many equal bands (1..64), each
+  int32_t bands;             /* CSR, SELL and CSR5: split the columns into this many equal bands (1..64), each
                                 converted to the format on its own over all M rows and run one after
                                 another, so each launch gathers from one slice of x that fits the L2; the
                                 band products are added in band order (FP64) by a final pass.  0 or 1 =
-                                no split (default); other formats return UNSUPPORTED for bands > 1 */
+                                no split (default); ELL and HYB return UNSUPPORTED for bands > 1 */
 } spmv_params_t;
 
 #define SPMV_FLAG_NO_CHECK 1u /* skip the column checks of spmv_mat_from_csr (ptr is always checked) */
@@ -126,7 +126,10 @@ spmv_status_t spmv_mat_from_coo(int64_t M, int64_t N, int64_t n, const int32_t* 
                                 spmv_mat_t* out);
 
 /* Convert a CSR handle to fmt (Sec. II-B; Table I): a new handle.  p may be
- * NULL (defaults).  ELL/SELL/HYB above the byte cap -> TOO_LARGE.
+ * NULL (defaults).  ELL/SELL/HYB above the byte cap -> TOO_LARGE.  The source
+ * must be a CSR handle without column bands (INVALID_ARG otherwise); so must
+ * the handles given to spmv_batch_create, spmv_autotune and spmv_features
+ * (INVALID_ARG) and to spmv_spmm (UNSUPPORTED).
  * Conversion runs on the device; it synchronises s (sizes come back). */
 spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* p, spmv_stream_t s,
                            spmv_mat_t* out);
@@ -142,8 +145,8 @@ spmv_status_t spmv_to_csr(spmv_mat_t A, int32_t* ptr, int32_t* col, void* val, i
  * "y_off","seg_off","tile_col","tile_val","tail_col","tail_val" (CSR5);
  * "band_ptr","band_col","band_val" (CSR built with SPMV_FLAG_CSR_BANDS:
  * 8 row-pointer arrays of M+1, then the bands' entries band after band).
- * A SELL or CSR5 handle built with bands > 1 has no arrays of its own;
- * band b's are "band<b>.sell_col", "band<b>.tile_ptr" etc. (band b holds
+ * A CSR, SELL or CSR5 handle built with bands > 1 has no arrays of its own;
+ * band b's are "band<b>.col", "band<b>.sell_col", "band<b>.tile_ptr" etc. (band b holds
  * the columns [b*ceil(N/bands), (b+1)*ceil(N/bands)).
  * spmv_array_bytes reports the size; export fails with INVALID_ARG when
  * bytes is smaller.  Synchronises s. */
@@ -221,8 +224,9 @@ spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int r
                                 spmv_stream_t s, double* ms);
 
 /* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: row
- * blocks, wave units, linear order, XCD bands, wave tiles, V lanes per row;
- * HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma; SELL sigma in
+ * blocks, wave units, linear order, XCD bands, wave tiles, V lanes per row,
+ * and, when x exceeds 4 MiB, row blocks and wave tiles over 2 and 4 column
+ * bands; HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma; SELL sigma in
  * {1, C, 8C, 256C, M}, M being one window over all rows, and, when x exceeds
  * 8 MiB, column bands of at most 8 MiB of x with sigma = M; CSR5: also such
  * column bands) on x/y and write the

@@ -94,6 +94,30 @@ static spmv_status_t build_handle(spmv_mat_t* out, F&& f) {
   return SPMV_OK;
 }
 
+
+// a CSR handle of its own (copies of src's arrays) with the kernel variant's
+// tables: row blocks, wave units, and, by flag, wave tiles or XCD bands
+spmv_status_t convert_csr(spmv_mat_s* src, spmv_mat_s* A, hipStream_t st) {
+  const int V = A->params.csr_lanes_per_row;
+  if (V < 0 || V > 64 || (V & (V - 1))) return fail(SPMV_ERR_UNSUPPORTED, "csr_lanes_per_row=%d", V);
+  SPMV_TRY(mat_alloc(A, (void**)&A->ptr, sizeof(int32_t) * (A->M + 1)));
+  SPMV_TRY(mat_alloc(A, (void**)&A->col, sizeof(int32_t) * A->nnz));
+  SPMV_TRY(mat_alloc(A, &A->val, (size_t)A->sv * A->nnz));
+  SPMV_HIP(hipMemcpyAsync(A->ptr, src->ptr, sizeof(int32_t) * (A->M + 1), hipMemcpyDeviceToDevice, st));
+  if (A->nnz) {
+    SPMV_HIP(hipMemcpyAsync(A->col, src->col, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToDevice, st));
+    SPMV_HIP(hipMemcpyAsync(A->val, src->val, (size_t)A->sv * A->nnz, hipMemcpyDeviceToDevice, st));
+  }
+  SPMV_TRY(csr_build_blocks(A, st));
+  A->bytes_fmt = bytes_min(A);
+  if ((A->params.flags & SPMV_FLAG_CSR_TILES) && V == 0) SPMV_TRY(csr_build_tiles(A, st));
+  if (A->params.flags & SPMV_FLAG_CSR_BANDS) {
+    SPMV_TRY(csr_build_bands(A, st));
+    A->bytes_fmt += (int64_t)(A->nbands - 1) * 4 * (A->M + 1);  // one row pointer per band
+  }
+  SPMV_HIP(hipStreamSynchronize(st));
+  return SPMV_OK;
+}
 }  // namespace spmv
 
 using namespace spmv;
@@ -137,8 +161,10 @@ spmv_status_t spmv_mat_from_coo(int64_t M, int64_t N, int64_t n, const int32_t* 
   });
 }
 
+
 spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* p, spmv_stream_t s, spmv_mat_t* out) {
-  if (!csr || csr->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_INVALID_ARG, "convert needs a CSR handle");
+  if (!csr || csr->fmt != SPMV_FMT_CSR || !csr->sub.empty())
+    return fail(SPMV_ERR_INVALID_ARG, "convert needs a CSR handle without column bands");
   if ((int)fmt < 0 || (int)fmt >= SPMV_NUM_FORMATS) return fail(SPMV_ERR_INVALID_ARG, "format %d", (int)fmt);
   hipStream_t st = hs(s);
   return build_handle(out, [&](spmv_mat_s* A) -> spmv_status_t {
@@ -151,25 +177,7 @@ spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* 
     resolve_params(p, &A->params);
     if (A->params.bands > 1) return convert_banded(csr, A, st);
     switch (fmt) {
-      case SPMV_FMT_CSR: {
-        const int V = A->params.csr_lanes_per_row;
-        if (V < 0 || V > 64 || (V & (V - 1))) return fail(SPMV_ERR_UNSUPPORTED, "csr_lanes_per_row=%d", V);
-        SPMV_TRY(mat_alloc(A, (void**)&A->ptr, sizeof(int32_t) * (A->M + 1)));
-        SPMV_TRY(mat_alloc(A, (void**)&A->col, sizeof(int32_t) * A->nnz));
-        SPMV_TRY(mat_alloc(A, &A->val, (size_t)A->sv * A->nnz));
-        SPMV_HIP(hipMemcpyAsync(A->ptr, csr->ptr, sizeof(int32_t) * (A->M + 1), hipMemcpyDeviceToDevice, st));
-        SPMV_HIP(hipMemcpyAsync(A->col, csr->col, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToDevice, st));
-        SPMV_HIP(hipMemcpyAsync(A->val, csr->val, (size_t)A->sv * A->nnz, hipMemcpyDeviceToDevice, st));
-        SPMV_TRY(csr_build_blocks(A, st));
-        A->bytes_fmt = bytes_min(A);
-        if ((A->params.flags & SPMV_FLAG_CSR_TILES) && V == 0) SPMV_TRY(csr_build_tiles(A, st));
-        if (A->params.flags & SPMV_FLAG_CSR_BANDS) {
-          SPMV_TRY(csr_build_bands(A, st));
-          A->bytes_fmt += (int64_t)(A->nbands - 1) * 4 * (A->M + 1);  // one row pointer per band
-        }
-        SPMV_HIP(hipStreamSynchronize(st));
-        return SPMV_OK;
-      }
+      case SPMV_FMT_CSR: return convert_csr(csr, A, st);
       case SPMV_FMT_ELL: return convert_ell(csr, A, st);
       case SPMV_FMT_SELL: return convert_sell(csr, A, st);
       case SPMV_FMT_HYB: return convert_hyb(csr, A, st);

@@ -1,4 +1,4 @@
-// Column bands (an execution layout of SELL-C-sigma and CSR5, not a format of
+// Column bands (an execution layout of CSR, SELL-C-sigma and CSR5, not a format of
 // the paper): the entries are split by column into nb equal bands, each band
 // is converted on its own (a matrix of all M rows holding only the band's
 // columns) and the bands run one after another.  Each launch then gathers
@@ -28,8 +28,8 @@ __global__ void k_band_sum(int64_t M, int nb, const T* __restrict__ part, T* __r
 
 spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   const int nb = A->params.bands;
-  if (A->fmt != SPMV_FMT_SELL && A->fmt != SPMV_FMT_CSR5)
-    return fail(SPMV_ERR_UNSUPPORTED, "column bands are implemented for SELL and CSR5");
+  if (A->fmt != SPMV_FMT_SELL && A->fmt != SPMV_FMT_CSR5 && A->fmt != SPMV_FMT_CSR)
+    return fail(SPMV_ERR_UNSUPPORTED, "column bands are implemented for CSR, SELL and CSR5");
   if (nb > 64) return fail(SPMV_ERR_UNSUPPORTED, "%d column bands (at most 64)", nb);
   const int64_t M = src->M, N = src->N, sv = A->sv;
   const int64_t bw = std::max<int64_t>(1, cdiv(N, nb));
@@ -62,8 +62,9 @@ spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     sub->nnz = band.nnz;
     sub->params = A->params;
     sub->params.bands = 1;
-    const spmv_status_t st = A->fmt == SPMV_FMT_SELL ? convert_sell(&band, sub.get(), s)
-                                                     : convert_csr5(&band, sub.get(), s);
+    const spmv_status_t st = A->fmt == SPMV_FMT_SELL   ? convert_sell(&band, sub.get(), s)
+                             : A->fmt == SPMV_FMT_CSR5 ? convert_csr5(&band, sub.get(), s)
+                                                       : convert_csr(&band, sub.get(), s);
     A->owned.insert(A->owned.end(), sub->owned.begin(), sub->owned.end());  // freed with the handle
     sub->owned.clear();
     if (st != SPMV_OK) return st;
@@ -140,7 +141,15 @@ spmv_status_t banded_to_csr(spmv_mat_s* A, int32_t* ptr, int32_t* col, void* val
     int32_t* pb = bp.as<int32_t>() + (int64_t)b * (M + 1);
     int32_t* cb = bc.as<int32_t>() + off[b];
     void* vb = (char*)bv.p + (size_t)sv * off[b];
-    SPMV_TRY(B->fmt == SPMV_FMT_CSR5 ? csr5_to_csr(B, pb, cb, vb, s) : ell_sell_hyb_to_csr(B, pb, cb, vb, s));
+    if (B->fmt == SPMV_FMT_CSR) {
+      SPMV_HIP(hipMemcpyAsync(pb, B->ptr, sizeof(int32_t) * (M + 1), hipMemcpyDeviceToDevice, s));
+      if (B->nnz) {
+        SPMV_HIP(hipMemcpyAsync(cb, B->col, sizeof(int32_t) * B->nnz, hipMemcpyDeviceToDevice, s));
+        SPMV_HIP(hipMemcpyAsync(vb, B->val, (size_t)sv * B->nnz, hipMemcpyDeviceToDevice, s));
+      }
+    } else {
+      SPMV_TRY(B->fmt == SPMV_FMT_CSR5 ? csr5_to_csr(B, pb, cb, vb, s) : ell_sell_hyb_to_csr(B, pb, cb, vb, s));
+    }
     off[b + 1] = off[b] + B->nnz;
   }
   SPMV_TRY(doff.alloc(sizeof(int64_t) * (nb + 1)));

@@ -45,7 +45,8 @@ spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* ou
   if (!A || n <= 0 || !out) return fail(SPMV_ERR_INVALID_ARG, "batch arguments");
   *out = nullptr;
   for (int32_t i = 0; i < n; ++i) {
-    if (!A[i] || A[i]->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_INVALID_ARG, "batch matrix %d is not CSR", i);
+    if (!A[i] || A[i]->fmt != SPMV_FMT_CSR || !A[i]->sub.empty())
+      return fail(SPMV_ERR_INVALID_ARG, "batch matrix %d is not a CSR handle without column bands", i);
     if (A[i]->dt != A[0]->dt) return fail(SPMV_ERR_INVALID_ARG, "batch mixes dtypes");
   }
   spmv_batch_s* b = new (std::nothrow) spmv_batch_s();
@@ -120,7 +121,7 @@ static std::map<TuneKey, std::pair<spmv_params_t, double>> g_tune_cache;
 
 spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void* y, int64_t scrub_bytes, int reps,
                             spmv_params_t* inout, double* ms_out, spmv_stream_t s) {
-  if (!csr || csr->fmt != SPMV_FMT_CSR || !inout) return fail(SPMV_ERR_INVALID_ARG, "autotune arguments");
+  if (!csr || csr->fmt != SPMV_FMT_CSR || !csr->sub.empty() || !inout) return fail(SPMV_ERR_INVALID_ARG, "autotune arguments");
   if (csr->M && (!y || (csr->N && !x))) return fail(SPMV_ERR_INVALID_ARG, "null x or y");
   if (reps < 3) reps = 3;
   hipStream_t st = hs(s);
@@ -173,6 +174,18 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
         p.flags = (p.flags & ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR | SPMV_FLAG_CSR_BANDS)) | SPMV_FLAG_CSR_TILES;
       });
       for (int V : {4, 8, 16, 32}) add([V](spmv_params_t& p) { p.csr_lanes_per_row = V; });
+      // x larger than 4 MiB: row blocks and wave tiles over 2 and 4 column
+      // bands.  Measured, 2 bands paid off from about 8 MB of x on (a 4 MB
+      // slice fits an XCD's L2) and 4 bands on x of 128 MB (a 32 MB slice
+      // stays in the Infinity Cache); more bands lost to the extra passes.
+      if (csr->M && csr->N * (int64_t)csr->sv > ((int64_t)4 << 20))
+        for (int nb : {2, 4})
+          for (uint32_t tiles : {0u, (uint32_t)SPMV_FLAG_CSR_TILES})
+            add([nb, tiles](spmv_params_t& p) {
+              p.csr_lanes_per_row = 0;
+              p.flags = (p.flags & ~(SPMV_FLAG_CSR_WAVES | SPMV_FLAG_LINEAR | SPMV_FLAG_CSR_BANDS | SPMV_FLAG_CSR_TILES)) | tiles;
+              p.bands = nb;
+            });
       break;
     case SPMV_FMT_CSR5:
       for (int sg : {4, 8, 16, 32}) add([sg](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = 1; });

@@ -264,6 +264,7 @@ spmv_status_t run_csr5(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
 spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s);
 spmv_status_t dispatch_run(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
 spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
+spmv_status_t convert_csr(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s);
 spmv_status_t run_banded(spmv_mat_s* A, const void* x, void* y, hipStream_t s);
 spmv_status_t banded_to_csr(spmv_mat_s* A, int32_t* ptr, int32_t* col, void* val, hipStream_t s);
 

@@ -849,7 +849,7 @@ static void launch_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int6
 }
 
 spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {
-  if (A->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_UNSUPPORTED, "spmm runs on CSR handles");
+  if (A->fmt != SPMV_FMT_CSR || !A->sub.empty()) return fail(SPMV_ERR_UNSUPPORTED, "spmm runs on CSR handles without column bands");
   if (k < 1 || k > 64 || ldx < k || ldy < k) return fail(SPMV_ERR_INVALID_ARG, "spmm needs 1 <= k <= 64, ld >= k");
   if (A->M == 0) return SPMV_OK;
   // 16-byte lanes (2 FP64 or 4 FP32 columns) where k, the leading

@@ -236,7 +236,8 @@ static void* g_feat_ws = nullptr;
 static size_t g_feat_bytes = 0;
 
 spmv_status_t features(spmv_mat_s* A, double* out_host, hipStream_t s) {
-  if (A->fmt != SPMV_FMT_CSR) return fail(SPMV_ERR_INVALID_ARG, "features need a CSR handle");
+  if (A->fmt != SPMV_FMT_CSR || !A->sub.empty())
+    return fail(SPMV_ERR_INVALID_ARG, "features need a CSR handle without column bands");
   const int64_t M = A->M;
   std::lock_guard<std::mutex> lock(g_feat_mu);
   auto reserve = [&](size_t bytes) -> spmv_status_t {

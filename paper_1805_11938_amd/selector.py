@@ -409,7 +409,7 @@ def compare_classifiers(records, dtype="f64", test=None, seed=0):
     return out
 
 
-PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags"), "csr5": ("csr5_omega", "csr5_sigma", "bands"), "ell": (),
+PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags", "bands"), "csr5": ("csr5_omega", "csr5_sigma", "bands"), "ell": (),
               "sell": ("sell_C", "sell_sigma", "bands"), "hyb": ("hyb_K",)}
 
 

@@ -44,6 +44,9 @@ FORMAT_CONFIGS = [
     ("csr", {"flags": 4}),
     ("csr", {"flags": 16}),
     ("csr", {"flags": 32}),
+    ("csr", {"bands": 3}),
+    ("csr", {"bands": 4, "flags": 32}),
+    ("csr", {"bands": 2, "csr_lanes_per_row": 4}),
     ("csr5", {}),
     ("csr5", {"csr5_sigma": 4}),
     ("csr5", {"csr5_sigma": 32}),

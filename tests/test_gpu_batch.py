@@ -121,6 +121,26 @@ def test_autotune_picks_a_valid_configuration(torch, fmt):
         assert p["csr5_sigma"] in (4, 8, 16, 32)
 
 
+def test_autotune_csr_over_column_bands(torch):
+    """x of 5.6 MB: the CSR grid includes row blocks and wave tiles over 2
+    and 4 column bands; whatever wins converts and runs to the bar."""
+    A = synth.zipf_rows(40_000, 700_000, 2.0, 12, 3000, 11, 12)
+    x64 = synth.vector(A.N, 2)
+    yref, den = reference(A, x64, 0)
+    Ad = S.Matrix.from_host(A)
+    x = device_vec(x64, 0)
+    y = torch.empty(A.M, dtype=torch.float64, device="cuda")
+    p, ms = Ad.autotune("csr", x, y, scrub_bytes=64 << 20, reps=3)
+    assert ms > 0 and p["bands"] in (1, 2, 4)
+    for nb in (2, 4):
+        for fl in (0, 32):
+            out = Ad.convert("csr", bands=nb, flags=fl).run(x).cpu().numpy()
+            assert rowwise_err(out, yref, den) <= TOL[0], (nb, fl)
+    out = Ad.convert("csr", **p).run(x).cpu().numpy()
+    assert rowwise_err(out, yref, den) <= TOL[0]
+    S.lib().spmv_autotune_cache_clear()
+
+
 def test_autotune_cache_by_structure(torch):
     import time
     A = synth.zipf_rows(30_000, 30_000, 2.0, 12, 2000, 8, 9)

@@ -170,6 +170,15 @@ def test_device_conversions_bit_identical(torch, ci):
                 assert np.array_equal(Sm.export(f"band{b}.sell_perm", np.int32), o["perm"]), (name, nb, b)
         with pytest.raises(S.SpmvError):
             Sm.export("sell_col", np.int32)  # a banded handle has no arrays of its own
+    for nb, fl in [(3, 0), (4, 32)]:
+        Cb = Ad.convert("csr", bands=nb, flags=fl)
+        w = -(-A.N // nb)
+        for b in range(nb):
+            bptr, bcol, bval = band(b, w)
+            assert np.array_equal(Cb.export(f"band{b}.ptr", np.int32), bptr), (name, nb, b)
+            assert np.array_equal(Cb.export(f"band{b}.col", np.int32), bcol), (name, nb, b)
+            assert np.array_equal(Cb.export(f"band{b}.val", np.float64).view(np.uint64),
+                                  bval.view(np.uint64)), (name, nb, b)
     for sg, nb in [(16, 2), (4, 5)]:
         C5 = Ad.convert("csr5", csr5_sigma=sg, bands=nb)
         w = -(-A.N // nb)
@@ -275,10 +284,22 @@ def test_errors(torch):
     with pytest.raises(S.SpmvError) as e:
         S.Matrix.from_coo(2, 2, [0, 2], [0, 0], np.ones(2))
     assert e.value.status == -2
-    for fmt in ("csr", "ell", "hyb"):  # column bands are a SELL / CSR5 layout
+    for fmt in ("ell", "hyb"):  # column bands are a CSR / SELL / CSR5 layout
         with pytest.raises(S.SpmvError) as e:
             A.convert(fmt, bands=2)
         assert e.value.status == -5
+    # a CSR handle with column bands has no arrays of its own: it runs, but
+    # is no source for conversions, SpMM, batches or features
+    Cb = A.convert("csr", bands=2)
+    with pytest.raises(S.SpmvError) as e:
+        Cb.convert("sell")
+    assert e.value.status == -1
+    with pytest.raises(S.SpmvError) as e:
+        Cb.features()
+    assert e.value.status == -1
+    with pytest.raises(S.SpmvError) as e:
+        Cb.spmm(torch.ones((A.N, 2), dtype=torch.float64, device="cuda"))
+    assert e.value.status == -5
     Z = S.Matrix.from_host(synth.zipf_rows(20_000, 20_000, 2.0, 16, 5_000, 4, 5))
     with pytest.raises(S.SpmvError) as e:
         Z.convert("ell", max_bytes=1 << 20)
