@@ -76,8 +76,10 @@ typedef struct {
   int32_t bands;             /* CSR, SELL and CSR5: split the columns into this many equal bands (1..64), each
                                 converted to the format on its own over all M rows and run one after
                                 another, so each launch gathers from one slice of x that fits the L2; the
-                                band products are added in band order (FP64) by a final pass.  0 or 1 =
-                                no split (default); ELL and HYB return UNSUPPORTED for bands > 1 */
+                                band products are added in band order (FP64) by a final pass.  HYB: the
+                                COO tail is ordered by band (then row, column) and each band's pass adds
+                                onto y after the previous one.  0 or 1 = no split (default); ELL returns
+                                UNSUPPORTED for bands > 1 */
 } spmv_params_t;
 
 #define SPMV_FLAG_NO_CHECK 1u /* skip the column checks of spmv_mat_from_csr (ptr is always checked) */
@@ -141,7 +143,8 @@ spmv_status_t spmv_to_csr(spmv_mat_t A, int32_t* ptr, int32_t* col, void* val, i
 /* Copy a named internal array to host memory (golden tests).  Names:
  * "ptr","col","val" (CSR; CSR5 keeps CSR's ptr); "ell_col","ell_val"
  * (ELL and HYB, column-major M x K); "sell_perm","sell_cs","sell_col",
- * "sell_val"; "coo_row","coo_col","coo_val" (HYB); "tile_ptr","bit_flag",
+ * "sell_val"; "coo_row","coo_col","coo_val" (HYB; with bands > 1 ordered by
+ * band, then row and column); "tile_ptr","bit_flag",
  * "y_off","seg_off","tile_col","tile_val","tail_col","tail_val" (CSR5);
  * "band_ptr","band_col","band_val" (CSR built with SPMV_FLAG_CSR_BANDS:
  * 8 row-pointer arrays of M+1, then the bands' entries band after band).
@@ -226,7 +229,9 @@ spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int r
 /* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: row
  * blocks, wave units, linear order, XCD bands, wave tiles, V lanes per row,
  * and, when x exceeds 4 MiB, row blocks and wave tiles over 2 and 4 column
- * bands; HYB: K in {rule, p50, p75, p90, p99}; CSR5: sigma; SELL sigma in
+ * bands; HYB: K in {rule, p50, p75, p90, p99}, each also with the COO tail
+ * over 2 and 4 column bands when x exceeds 4 MiB (and 8 above 32 MiB);
+ * CSR5: sigma; SELL sigma in
  * {1, C, 8C, 256C, M}, M being one window over all rows, and, when x exceeds
  * 8 MiB, column bands of at most 8 MiB of x with sigma = M; CSR5: also such
  * column bands) on x/y and write the

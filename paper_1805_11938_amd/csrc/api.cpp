@@ -175,7 +175,7 @@ spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* 
     A->nnz = csr->nnz;
     A->sv = csr->sv;
     resolve_params(p, &A->params);
-    if (A->params.bands > 1) return convert_banded(csr, A, st);
+    if (A->params.bands > 1 && fmt != SPMV_FMT_HYB) return convert_banded(csr, A, st);
     switch (fmt) {
       case SPMV_FMT_CSR: return convert_csr(csr, A, st);
       case SPMV_FMT_ELL: return convert_ell(csr, A, st);

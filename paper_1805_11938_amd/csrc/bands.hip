@@ -83,8 +83,9 @@ spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     return fail(SPMV_ERR_TOO_LARGE, "%d column bands need %lld bytes (cap %lld)", nb,
                 (long long)(fmt_bytes + (int64_t)nb * M * sv), (long long)cap);
   SPMV_TRY(mat_alloc(A, &A->spart, (size_t)sv * nb * std::max<int64_t>(M, 1)));
-  // band arrays, x once, nb band products written and read back, y once
-  A->bytes_fmt = fmt_bytes + N * sv + 2 * (int64_t)nb * M * sv + M * sv;
+  // the bands' arrays, x once, y once (the band products in the scratch are
+  // traffic of this execution layout, not of the product: not counted)
+  A->bytes_fmt = fmt_bytes + N * sv + M * sv;
   SPMV_HIP(hipStreamSynchronize(s));
   return SPMV_OK;
 }

@@ -222,11 +222,19 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
         for (int64_t i = 0; i < csr->M; ++i) lens[i] = hp[i + 1] - hp[i];
         std::sort(lens.begin(), lens.end());
       }
-      add([](spmv_params_t& p) { p.hyb_K = -1; });
-      for (double q : {0.5, 0.75, 0.9, 0.99}) {
-        const int32_t K = csr->M ? lens[(size_t)(q * (double)(csr->M - 1))] : 0;
-        add([K](spmv_params_t& p) { p.hyb_K = K; });
-      }
+      // and, when x exceeds 4 MiB, each K with the COO tail over 2 and 4
+      // column bands (8 too when x exceeds 32 MiB).  Measured: 2 bands took
+      // zipf_1M's HYB from 191 to 159 us (8 MB of x), 4 bands rmat24's from
+      // 3.59 to 2.17 ms (134 MB); on x of about 8 MB with shorter tails, and
+      // in FP32 at 4 MB, bands lost.
+      std::vector<int32_t> Ks{-1};
+      for (double q : {0.5, 0.75, 0.9, 0.99}) Ks.push_back(csr->M ? lens[(size_t)(q * (double)(csr->M - 1))] : 0);
+      std::vector<int> nbs{1};
+      const int64_t xbytes = csr->N * (int64_t)csr->sv;
+      if (csr->M && xbytes > ((int64_t)4 << 20)) nbs.insert(nbs.end(), {2, 4});
+      if (csr->M && xbytes > ((int64_t)32 << 20)) nbs.push_back(8);
+      for (int nb : nbs)
+        for (int32_t K : Ks) add([K, nb](spmv_params_t& p) { p.hyb_K = K; p.bands = nb; });
       break;
     }
     default: return fail(SPMV_ERR_INVALID_ARG, "format %d", (int)fmt);

@@ -183,6 +183,9 @@ struct spmv_mat_s {
   double* coo_tail = nullptr;   // per COO tile: partial sum of its last row when it continues (run scratch)
   int32_t* coo_trow = nullptr;  // per COO tile: that last row
   int32_t* coo_tinfo = nullptr; // per COO tile: CT_TAIL / CT_SPAN / 0
+  // HYB with bands > 1: the COO entries are ordered by column band, then by
+  // row and column; band b's are [coo_boff[b], coo_boff[b+1]) (host, bands+1)
+  std::vector<int64_t> coo_boff;
 
   // CSR5
   int32_t omega = 0, c5sigma = 0;

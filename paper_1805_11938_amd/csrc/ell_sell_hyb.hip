@@ -840,21 +840,39 @@ __global__ __launch_bounds__(BS) void k_coo_tiles(int64_t ncoo, int64_t ntiles, 
   wave_tile_reduce<T, true>(t, nv, rr, cc, vv, rprev, rnext, x, y, head_part, tail_part, tail_row, tinfo);
 }
 
+// One COO pass over entries [e0, e0 + n) with tile scratch from tile tb on:
+// the tiles add their rows onto y, then the fix-up adds the rows that cross
+// tiles.  Passes on one stream run in order, so the column bands of a banded
+// tail add onto y one after another, in band order.
+template <typename T>
+static spmv_status_t coo_pass(spmv_mat_s* A, int64_t e0, int64_t n, int64_t tb, const void* x, void* y,
+                              hipStream_t s) {
+  const int64_t nt = cdiv(n, TILE_E);
+  launch(k_coo_tiles<T>, (unsigned)cdiv(nt, BS / WAVE), BS, s, n, nt, A->crow + e0, A->ccol + e0,
+         (const T*)A->cval + e0, (const T*)x, (T*)y, A->coo_head + tb, A->coo_tail + tb, A->coo_trow + tb,
+         A->coo_tinfo + tb);
+  SPMV_LAUNCH_CHECK();
+  if (nt > 1) {
+    launch(k_tile_fix<T, true>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt,
+           (const double*)A->coo_head + tb, (const double*)A->coo_tail + tb, (const int32_t*)A->coo_trow + tb,
+           (const int32_t*)A->coo_tinfo + tb, (T*)y);
+    SPMV_LAUNCH_CHECK();
+  }
+  return SPMV_OK;
+}
+
 template <typename T>
 static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   if (A->M == 0) return SPMV_OK;
   SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, !(A->params.flags & SPMV_FLAG_LINEAR), s));
-  if (A->ncoo > 0) {
-    const int64_t nt = cdiv(A->ncoo, TILE_E);
-    launch(k_coo_tiles<T>, (unsigned)cdiv(nt, BS / WAVE), BS, s, A->ncoo, nt, A->crow, A->ccol, (const T*)A->cval,
-           (const T*)x, (T*)y, A->coo_head, A->coo_tail, A->coo_trow, A->coo_tinfo);
-    SPMV_LAUNCH_CHECK();
-    if (nt > 1) {
-      launch(k_tile_fix<T, true>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt,
-             (const double*)A->coo_head, (const double*)A->coo_tail, (const int32_t*)A->coo_trow,
-             (const int32_t*)A->coo_tinfo, (T*)y);
-      SPMV_LAUNCH_CHECK();
-    }
+  if (A->ncoo == 0) return SPMV_OK;
+  if (A->coo_boff.empty()) return coo_pass<T>(A, 0, A->ncoo, 0, x, y, s);
+  int64_t tb = 0;
+  for (size_t b = 0; b + 1 < A->coo_boff.size(); ++b) {
+    const int64_t e0 = A->coo_boff[b], n = A->coo_boff[b + 1] - e0;
+    if (n == 0) continue;
+    SPMV_TRY(coo_pass<T>(A, e0, n, tb, x, y, s));
+    tb += cdiv(n, TILE_E);
   }
   return SPMV_OK;
 }
@@ -889,8 +907,74 @@ static spmv_status_t hyb_rule_k(spmv_mat_s* src, int64_t* K, hipStream_t s) {
   return SPMV_OK;
 }
 
+__global__ void k_coo_band_keys(int64_t n, const int32_t* ccol, int64_t bw, uint64_t* key, uint32_t* idx) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    key[i] = (uint64_t)(ccol[i] / bw);
+    idx[i] = (uint32_t)i;
+  }
+}
+
+template <typename T>
+__global__ void k_coo_gather(int64_t n, const uint32_t* idx, const int32_t* r0, const int32_t* c0, const T* v0,
+                             int32_t* r1, int32_t* c1, T* v1) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = idx[i];
+    r1[i] = r0[j];
+    c1[i] = c0[j];
+    v1[i] = v0[j];
+  }
+}
+
+// first index whose (ascending) key is >= b, for b = 0..nb
+__global__ void k_key_bounds(int64_t n, const uint64_t* key, int nb, int64_t* bound) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nb) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (key[mid] < (uint64_t)b) lo = mid + 1;
+    else hi = mid;
+  }
+  bound[b] = lo;
+}
+
+// Reorder a row-major COO tail (r, c, v) into A's arrays by column band,
+// stably, so each band stays in row-major order; record the band offsets.
+static spmv_status_t coo_order_by_band(spmv_mat_s* A, int nb, const int32_t* r, const int32_t* c, const void* v,
+                                       hipStream_t s) {
+  const int64_t n = A->ncoo;
+  const int64_t bw = std::max<int64_t>(1, cdiv(A->N, nb));
+  A->band_w = bw;
+  if (n >= ((int64_t)1 << 32)) return fail(SPMV_ERR_TOO_LARGE, "%lld COO entries", (long long)n);
+  DTmp k1, k2, v1, v2, bd;
+  SPMV_TRY(k1.alloc(sizeof(uint64_t) * n));
+  SPMV_TRY(k2.alloc(sizeof(uint64_t) * n));
+  SPMV_TRY(v1.alloc(sizeof(uint32_t) * n));
+  SPMV_TRY(v2.alloc(sizeof(uint32_t) * n));
+  SPMV_TRY(bd.alloc(sizeof(int64_t) * (nb + 1)));
+  uint64_t* key = k1.as<uint64_t>();
+  uint32_t* idx = v1.as<uint32_t>();
+  k_coo_band_keys<<<grid_rows(n), BS, 0, s>>>(n, c, bw, key, idx);
+  SPMV_LAUNCH_CHECK();
+  SPMV_TRY(radix_sort_pairs(&key, &idx, k2.as<uint64_t>(), v2.as<uint32_t>(), n, bits_for((uint64_t)(nb - 1)), s));
+  if (A->dt == SPMV_F64)
+    k_coo_gather<double><<<grid_rows(n), BS, 0, s>>>(n, idx, r, c, (const double*)v, A->crow, A->ccol,
+                                                     (double*)A->cval);
+  else
+    k_coo_gather<float><<<grid_rows(n), BS, 0, s>>>(n, idx, r, c, (const float*)v, A->crow, A->ccol,
+                                                    (float*)A->cval);
+  SPMV_LAUNCH_CHECK();
+  k_key_bounds<<<1, 128, 0, s>>>(n, key, nb, bd.as<int64_t>());
+  SPMV_LAUNCH_CHECK();
+  A->coo_boff.assign(nb + 1, 0);
+  SPMV_TRY(copy_to_host(A->coo_boff.data(), bd.p, sizeof(int64_t) * (nb + 1), s));
+  return SPMV_OK;
+}
+
 spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   const int64_t M = src->M;
+  const int nb = A->params.bands;
+  if (nb > 64) return fail(SPMV_ERR_UNSUPPORTED, "%d column bands (at most 64)", nb);
   int64_t K = A->params.hyb_K;
   if (K < 0) SPMV_TRY(hyb_rule_k(src, &K, s));
   A->params.hyb_K = (int32_t)K;
@@ -908,18 +992,34 @@ spmv_status_t convert_hyb(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   SPMV_TRY(mat_alloc(A, (void**)&A->crow, sizeof(int32_t) * A->ncoo));
   SPMV_TRY(mat_alloc(A, (void**)&A->ccol, sizeof(int32_t) * A->ncoo));
   SPMV_TRY(mat_alloc(A, &A->cval, (size_t)A->sv * A->ncoo));
+  const bool banded = nb > 1 && A->ncoo > 0;
   if (A->ncoo) {
+    // row-major tail, written straight into the handle or, when banded,
+    // into temporaries that are then reordered by column band
+    DTmp tr, tcol, tv;
+    int32_t* crow = A->crow;
+    int32_t* ccol = A->ccol;
+    void* cval = A->cval;
+    if (banded) {
+      SPMV_TRY(tr.alloc(sizeof(int32_t) * A->ncoo));
+      SPMV_TRY(tcol.alloc(sizeof(int32_t) * A->ncoo));
+      SPMV_TRY(tv.alloc((size_t)A->sv * A->ncoo));
+      crow = tr.as<int32_t>();
+      ccol = tcol.as<int32_t>();
+      cval = tv.p;
+    }
     const unsigned gw = (unsigned)std::min<int64_t>(cdiv(M, BS / WAVE), 1 << 20);
     if (A->dt == SPMV_F64)
       k_hyb_fill_coo<double><<<gw, BS, 0, s>>>(M, K, src->ptr, src->col, (const double*)src->val, off.as<int64_t>(),
-                                               A->crow, A->ccol, (double*)A->cval);
+                                               crow, ccol, (double*)cval);
     else
       k_hyb_fill_coo<float><<<gw, BS, 0, s>>>(M, K, src->ptr, src->col, (const float*)src->val, off.as<int64_t>(),
-                                              A->crow, A->ccol, (float*)A->cval);
+                                              crow, ccol, (float*)cval);
     SPMV_LAUNCH_CHECK();
+    if (banded) SPMV_TRY(coo_order_by_band(A, nb, crow, ccol, cval, s));
   }
-  {  // per-tile scratch of the COO pass
-    const int64_t nt = std::max<int64_t>(cdiv(A->ncoo, TILE_E), 1);
+  {  // per-tile scratch of the COO pass (each band's tiles start afresh)
+    const int64_t nt = std::max<int64_t>(cdiv(A->ncoo, TILE_E) + (banded ? nb : 0), 1);
     SPMV_TRY(mat_alloc(A, (void**)&A->coo_head, sizeof(double) * nt));
     SPMV_TRY(mat_alloc(A, (void**)&A->coo_tail, sizeof(double) * nt));
     SPMV_TRY(mat_alloc(A, (void**)&A->coo_trow, sizeof(int32_t) * nt));
@@ -939,6 +1039,13 @@ static spmv_status_t to_csr_t(spmv_mat_s* A, int32_t* ptr, int32_t* col, T* val,
 __global__ void k_hyb_len(int64_t M, const int32_t* ell_len, const int32_t* tail_cnt, int32_t* len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
     len[i] = ell_len[i] + tail_cnt[i];
+}
+
+__global__ void k_coo_row_keys(int64_t n, const int32_t* crow, uint64_t* key, uint32_t* idx) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    key[i] = (uint64_t)crow[i];
+    idx[i] = (uint32_t)i;
+  }
 }
 
 __global__ void k_coo_rowcount(int64_t n, const int32_t* crow, int32_t* cnt) {
@@ -977,13 +1084,40 @@ static spmv_status_t to_csr_t(spmv_mat_s* A, int32_t* ptr, int32_t* col, T* val,
       }
       return SPMV_OK;
     }
+    // a banded tail goes back to row-major order first: a stable sort by
+    // row keeps each row's bands in band order, i.e. its columns ascending
+    const int32_t* crow = A->crow;
+    const int32_t* ccol = A->ccol;
+    const T* cval = (const T*)A->cval;
+    DTmp k1, k2, v1, v2, sr, sc, svv;
+    if (!A->coo_boff.empty()) {
+      const int64_t n = A->ncoo;
+      SPMV_TRY(k1.alloc(sizeof(uint64_t) * n));
+      SPMV_TRY(k2.alloc(sizeof(uint64_t) * n));
+      SPMV_TRY(v1.alloc(sizeof(uint32_t) * n));
+      SPMV_TRY(v2.alloc(sizeof(uint32_t) * n));
+      SPMV_TRY(sr.alloc(sizeof(int32_t) * n));
+      SPMV_TRY(sc.alloc(sizeof(int32_t) * n));
+      SPMV_TRY(svv.alloc(sizeof(T) * n));
+      uint64_t* key = k1.as<uint64_t>();
+      uint32_t* idx = v1.as<uint32_t>();
+      k_coo_row_keys<<<grid_rows(n), BS, 0, s>>>(n, A->crow, key, idx);
+      SPMV_LAUNCH_CHECK();
+      SPMV_TRY(radix_sort_pairs(&key, &idx, k2.as<uint64_t>(), v2.as<uint32_t>(), n, bits_for((uint64_t)(M - 1)), s));
+      k_coo_gather<T><<<grid_rows(n), BS, 0, s>>>(n, idx, A->crow, A->ccol, (const T*)A->cval, sr.as<int32_t>(),
+                                                  sc.as<int32_t>(), svv.as<T>());
+      SPMV_LAUNCH_CHECK();
+      crow = sr.as<int32_t>();
+      ccol = sc.as<int32_t>();
+      cval = svv.as<T>();
+    }
     DTmp cnt, tot, toff;
     SPMV_TRY(cnt.alloc(sizeof(int32_t) * M));
     SPMV_TRY(tot.alloc(sizeof(int32_t) * M));
     SPMV_TRY(toff.alloc(sizeof(int64_t) * (M + 1)));
     SPMV_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * M, s));
     const unsigned gc = grid_rows(A->ncoo);
-    k_coo_rowcount<<<gc, BS, 0, s>>>(A->ncoo, A->crow, cnt.as<int32_t>());
+    k_coo_rowcount<<<gc, BS, 0, s>>>(A->ncoo, crow, cnt.as<int32_t>());
     SPMV_LAUNCH_CHECK();
     SPMV_TRY(scan_i32_to_i64(cnt.as<int32_t>(), toff.as<int64_t>(), M, s));  // first COO entry of each row
     k_hyb_len<<<g, BS, 0, s>>>(M, len.as<int32_t>(), cnt.as<int32_t>(), tot.as<int32_t>());
@@ -991,8 +1125,8 @@ static spmv_status_t to_csr_t(spmv_mat_s* A, int32_t* ptr, int32_t* col, T* val,
     SPMV_TRY(scan_i32_to_i32(tot.as<int32_t>(), ptr, M, s));
     k_ell_to_csr<T><<<g, BS, 0, s>>>(M, A->ecol, (const T*)A->eval, len.as<int32_t>(), ptr, col, val);
     SPMV_LAUNCH_CHECK();
-    k_coo_to_csr<T><<<gc, BS, 0, s>>>(A->ncoo, A->crow, A->ccol, (const T*)A->cval, ptr, len.as<int32_t>(),
-                                      toff.as<int64_t>(), col, val);
+    k_coo_to_csr<T><<<gc, BS, 0, s>>>(A->ncoo, crow, ccol, cval, ptr, len.as<int32_t>(), toff.as<int64_t>(), col,
+                                      val);
     SPMV_LAUNCH_CHECK();
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;

@@ -410,7 +410,7 @@ def compare_classifiers(records, dtype="f64", test=None, seed=0):
 
 
 PARAM_KEYS = {"csr": ("csr_lanes_per_row", "flags", "bands"), "csr5": ("csr5_omega", "csr5_sigma", "bands"), "ell": (),
-              "sell": ("sell_C", "sell_sigma", "bands"), "hyb": ("hyb_K",)}
+              "sell": ("sell_C", "sell_sigma", "bands"), "hyb": ("hyb_K", "bands")}
 
 
 def merge(out_path, parts):

@@ -66,4 +66,7 @@ FORMAT_CONFIGS = [
     ("hyb", {}),
     ("hyb", {"hyb_K": 0}),
     ("hyb", {"hyb_K": 2}),
+    ("hyb", {"bands": 3}),
+    ("hyb", {"hyb_K": 1, "bands": 2}),
+    ("hyb", {"hyb_K": 0, "bands": 4}),
 ]

@@ -123,7 +123,8 @@ def test_autotune_picks_a_valid_configuration(torch, fmt):
 
 def test_autotune_csr_over_column_bands(torch):
     """x of 5.6 MB: the CSR grid includes row blocks and wave tiles over 2
-    and 4 column bands; whatever wins converts and runs to the bar."""
+    and 4 column bands, the HYB grid tails over 2 and 4 bands; whatever wins
+    converts and runs to the bar."""
     A = synth.zipf_rows(40_000, 700_000, 2.0, 12, 3000, 11, 12)
     x64 = synth.vector(A.N, 2)
     yref, den = reference(A, x64, 0)
@@ -137,6 +138,11 @@ def test_autotune_csr_over_column_bands(torch):
             out = Ad.convert("csr", bands=nb, flags=fl).run(x).cpu().numpy()
             assert rowwise_err(out, yref, den) <= TOL[0], (nb, fl)
     out = Ad.convert("csr", **p).run(x).cpu().numpy()
+    assert rowwise_err(out, yref, den) <= TOL[0]
+    # HYB: every K also with its COO tail over 2 and 4 bands
+    p, ms = Ad.autotune("hyb", x, y, scrub_bytes=64 << 20, reps=3)
+    assert ms > 0 and p["bands"] in (1, 2, 4)
+    out = Ad.convert("hyb", **p).run(x).cpu().numpy()
     assert rowwise_err(out, yref, den) <= TOL[0]
     S.lib().spmv_autotune_cache_clear()
 

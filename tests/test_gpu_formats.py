@@ -198,6 +198,17 @@ def test_device_conversions_bit_identical(torch, ci):
         assert np.array_equal(H.export("coo_row", np.int32), o["coo_row"])
         assert np.array_equal(H.export("coo_col", np.int32), o["coo_col"])
         assert np.array_equal(H.export("coo_val", np.float64).view(np.uint64), o["coo_val"].view(np.uint64))
+    # HYB with its COO tail over column bands: the oracle's tail, stably
+    # ordered by band (col // w), so each band stays row-major
+    for Kh, nb in [(1, 3), (None, 2), (0, 5)]:
+        o = oracle.csr_to_hyb(M, A.ptr, A.col, A.val, Kh)
+        H = Ad.convert("hyb", bands=nb, **({} if Kh is None else {"hyb_K": Kh}))
+        order = np.argsort(o["coo_col"] // -(-A.N // nb), kind="stable")
+        assert np.array_equal(H.export("ell_col", np.int32), o["ell_col"]), (name, Kh, nb)
+        assert np.array_equal(H.export("coo_row", np.int32), o["coo_row"][order]), (name, Kh, nb)
+        assert np.array_equal(H.export("coo_col", np.int32), o["coo_col"][order]), (name, Kh, nb)
+        assert np.array_equal(H.export("coo_val", np.float64).view(np.uint64),
+                              o["coo_val"][order].view(np.uint64)), (name, Kh, nb)
     # CSR5
     for w, s in [(64, 16), (32, 4), (2, 2)]:
         o = oracle.csr_to_csr5(M, A.ptr, A.col, A.val, w, s)
@@ -284,9 +295,12 @@ def test_errors(torch):
     with pytest.raises(S.SpmvError) as e:
         S.Matrix.from_coo(2, 2, [0, 2], [0, 0], np.ones(2))
     assert e.value.status == -2
-    for fmt in ("ell", "hyb"):  # column bands are a CSR / SELL / CSR5 layout
+    with pytest.raises(S.SpmvError) as e:  # ELL has no column-band layout
+        A.convert("ell", bands=2)
+    assert e.value.status == -5
+    for fmt in ("csr", "csr5", "sell", "hyb"):
         with pytest.raises(S.SpmvError) as e:
-            A.convert(fmt, bands=2)
+            A.convert(fmt, bands=65)
         assert e.value.status == -5
     # a CSR handle with column bands has no arrays of its own: it runs, but
     # is no source for conversions, SpMM, batches or features
