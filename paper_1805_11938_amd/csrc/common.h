@@ -206,7 +206,7 @@ struct spmv_mat_s {
   int32_t* chains = nullptr;     // (row, t_begin, t_end) triples for the carry fix-up
   double* carry = nullptr;       // ntiles + 1 partial sums (run scratch)
 
-  // Column bands (params.bands > 1, SELL and CSR5): sub[b] is the handle's
+  // Column bands (params.bands > 1, CSR, SELL and CSR5): sub[b] is the handle's
   // format built from the entries with col in [b*band_w, (b+1)*band_w), over
   // all M rows; this handle holds no format arrays of its own
   std::vector<std::unique_ptr<spmv_mat_s>> sub;
