@@ -113,17 +113,21 @@ __global__ void k_bands_len(int64_t M, int nb, const int32_t* bptr, int32_t* len
   }
 }
 
+// one wave per row, the lanes copying consecutive entries of each band
 template <typename T>
 __global__ void k_bands_merge(int64_t M, int nb, const int32_t* bptr, const int64_t* off, const int32_t* bcol,
                               const T* bval, const int32_t* ptr, int32_t* col, T* val) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+  const int lane = __lane_id();
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < M; r += nw) {
     int64_t d = ptr[r];
     for (int b = 0; b < nb; ++b) {
       const int64_t a = off[b] + bptr[b * (M + 1) + r], e = off[b] + bptr[b * (M + 1) + r + 1];
-      for (int64_t k = a; k < e; ++k, ++d) {
-        col[d] = bcol[k];
-        val[d] = bval[k];
+      for (int64_t k = a + lane; k < e; k += WAVE) {
+        col[d + (k - a)] = bcol[k];
+        val[d + (k - a)] = bval[k];
       }
+      d += e - a;
     }
   }
 }
@@ -161,11 +165,12 @@ spmv_status_t banded_to_csr(spmv_mat_s* A, int32_t* ptr, int32_t* col, void* val
   }
   SPMV_TRY(scan_i32_to_i32(len.as<int32_t>(), ptr, M, s));
   if (M) {
+    const unsigned gw = (unsigned)std::min<int64_t>(cdiv(M, BS / WAVE), 1 << 20);
     if (A->dt == SPMV_F64)
-      k_bands_merge<double><<<grid_for(M), BS, 0, s>>>(M, nb, bp.as<int32_t>(), doff.as<int64_t>(), bc.as<int32_t>(),
+      k_bands_merge<double><<<gw, BS, 0, s>>>(M, nb, bp.as<int32_t>(), doff.as<int64_t>(), bc.as<int32_t>(),
                                                        (const double*)bv.p, ptr, col, (double*)val);
     else
-      k_bands_merge<float><<<grid_for(M), BS, 0, s>>>(M, nb, bp.as<int32_t>(), doff.as<int64_t>(), bc.as<int32_t>(),
+      k_bands_merge<float><<<gw, BS, 0, s>>>(M, nb, bp.as<int32_t>(), doff.as<int64_t>(), bc.as<int32_t>(),
                                                       (const float*)bv.p, ptr, col, (float*)val);
     SPMV_LAUNCH_CHECK();
   }

@@ -326,15 +326,20 @@ __global__ void k_band_count(int64_t M, const int32_t* ptr, const int32_t* col, 
   }
 }
 
+// one wave per row: the row's entries of each band go to that band's place,
+// the lanes copying consecutive entries (a row of 10^5 entries is not left
+// to one thread)
 template <typename T>
 __global__ void k_band_scatter(int64_t M, int nb, const int32_t* ptr, const int32_t* col, const T* val,
                                const int32_t* cnt, const int32_t* bptr, const int64_t* boff, int32_t* bcol, T* bval) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+  const int lane = __lane_id();
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < M; r += nw) {
     int64_t k = ptr[r];
     for (int b = 0; b < nb; ++b) {
       const int64_t dst = boff[b] + bptr[b * (M + 1) + r];
       const int32_t n = cnt[b * M + r];
-      for (int32_t q = 0; q < n; ++q) {
+      for (int32_t q = lane; q < n; q += WAVE) {
         bcol[dst + q] = col[k + q];
         bval[dst + q] = val[k + q];
       }
@@ -363,12 +368,13 @@ spmv_status_t csr_split_bands(const spmv_mat_s* src, int nb, int64_t bw, int32_t
   SPMV_TRY(doff.alloc(sizeof(int64_t) * (nb + 1)));
   SPMV_HIP(hipMemcpyAsync(doff.p, off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
   if (M) {
+    const unsigned gw = (unsigned)std::min<int64_t>(cdiv(M, BS / WAVE), 1 << 20);
     if (src->dt == SPMV_F64)
-      k_band_scatter<double><<<g, BS, 0, s>>>(M, nb, src->ptr, src->col, (const double*)src->val, cnt.as<int32_t>(),
-                                              bptr, doff.as<int64_t>(), bcol, (double*)bval);
+      k_band_scatter<double><<<gw, BS, 0, s>>>(M, nb, src->ptr, src->col, (const double*)src->val, cnt.as<int32_t>(),
+                                               bptr, doff.as<int64_t>(), bcol, (double*)bval);
     else
-      k_band_scatter<float><<<g, BS, 0, s>>>(M, nb, src->ptr, src->col, (const float*)src->val, cnt.as<int32_t>(),
-                                             bptr, doff.as<int64_t>(), bcol, (float*)bval);
+      k_band_scatter<float><<<gw, BS, 0, s>>>(M, nb, src->ptr, src->col, (const float*)src->val, cnt.as<int32_t>(),
+                                              bptr, doff.as<int64_t>(), bcol, (float*)bval);
     SPMV_LAUNCH_CHECK();
   }
   SPMV_HIP(hipStreamSynchronize(s));  // cnt and doff are freed on return
