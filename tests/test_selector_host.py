@@ -109,3 +109,31 @@ def test_conversion_pays_off_rule():
     assert not SEL.worth_converting(10.0, 3.0, 2.0, 10)
     assert SEL.worth_converting(10.0, 3.0, 2.0, 11)
     assert not SEL.worth_converting(0.0, 2.0, 3.0, 1000)  # a slower format never pays
+
+
+def test_merge_keeps_each_formats_own_parameters(tmp_path):
+    """Collection parts are joined by (matrix, dtype), later parts winning,
+    and each format keeps only its own parameters (column bands included
+    for CSR, CSR5, SELL and HYB)."""
+    import json
+    full = dict(csr_lanes_per_row=0, flags=32, bands=2, csr5_omega=64, csr5_sigma=16, sell_C=64,
+                sell_sigma=1000, hyb_K=3)
+    rec = dict(index=4, kind="zipf", M=10, N=10, nnz=20, dtype="f64", features=[0.0] * 12,
+               times_ms=[1.0, 2.0, None, 3.0, 4.0], ci_ms=[0.0] * 5,
+               params={f: dict(full) for f in SEL.CLASSES}, label=0)
+    rec["params"]["ell"] = None
+    a, b = tmp_path / "a.jsonl", tmp_path / "b.jsonl"
+    a.write_text(json.dumps(rec) + "\n")
+    rec2 = dict(rec, times_ms=[5.0, 2.0, None, 3.0, 4.0], label=1)
+    b.write_text(json.dumps(rec2) + "\n" + json.dumps(dict(rec, index=1)) + "\n")
+    out = tmp_path / "m.jsonl"
+    assert SEL.merge(str(out), [str(a), str(b)]) == 2
+    recs = SEL.load(str(out))
+    assert [r["index"] for r in recs] == [1, 4]
+    p = recs[1]["params"]
+    assert recs[1]["times_ms"][0] == 5.0 and recs[1]["times_ms"][2] == INF
+    assert p["csr"] == dict(csr_lanes_per_row=0, flags=32, bands=2)
+    assert p["csr5"] == dict(csr5_omega=64, csr5_sigma=16, bands=2)
+    assert p["sell"] == dict(sell_C=64, sell_sigma=1000, bands=2)
+    assert p["hyb"] == dict(hyb_K=3, bands=2)
+    assert p["ell"] is None
