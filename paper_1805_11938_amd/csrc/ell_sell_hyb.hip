@@ -330,15 +330,23 @@ __global__ void k_sell_width(int64_t M, int64_t nch, int C, const int32_t* ptr, 
   }
 }
 
+// A wave fills at most SELL_FILL slots of a chunk; a chunk holding very long
+// rows (C x width beyond that) gets extra waves for the rest, one per
+// SELL_FILL slots, so no single wave copies millions of slots.
+constexpr int64_t SELL_FILL = 16384;
+
+// One wave per unit: slots [q0, q0 + SELL_FILL) of one chunk, written
+// slot-major (coalesced) by all lanes together after the chunk's rows are
+// looked up once.  units == nullptr: unit u is chunk u from slot 0.
 template <typename T>
-__global__ __launch_bounds__(WAVE) void k_csr_to_sell(int64_t M, int64_t nchunks, int C, const int32_t* ptr,
+__global__ __launch_bounds__(WAVE) void k_csr_to_sell(int64_t M, int64_t nunits, int C, const int32_t* ptr,
                                                       const int32_t* col, const T* val, const int32_t* perm,
-                                                      const int64_t* cs, int32_t* scol, T* sval) {
-  // one wave per chunk: the chunk's rows are looked up once, then its C x w
-  // slots are written slot-major (coalesced) by all lanes together, so a
-  // chunk holding one very long row is filled in parallel
+                                                      const int64_t* cs, const int64_t* units, int32_t* scol,
+                                                      T* sval) {
   __shared__ int64_t ra[WAVE], rl[WAVE];
-  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+  for (int64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int64_t c = units ? units[2 * u] : u;
+    const int64_t q0 = units ? units[2 * u + 1] : 0;
     const int t = threadIdx.x;
     if (t < C) {
       const int64_t pos = c * C + t;
@@ -348,7 +356,8 @@ __global__ __launch_bounds__(WAVE) void k_csr_to_sell(int64_t M, int64_t nchunks
     }
     __syncthreads();
     const int64_t base = cs[c], n = cs[c + 1] - base;
-    for (int64_t q = t; q < n; q += WAVE) {
+    const int64_t q1 = n < q0 + SELL_FILL ? n : q0 + SELL_FILL;
+    for (int64_t q = q0 + t; q < q1; q += WAVE) {
       const int64_t k = q / C, p = q % C;
       if (k < rl[p]) {
         scol[base + q] = col[ra[p] + k];
@@ -668,6 +677,18 @@ __global__ void k_sell_items(int64_t nch, const int32_t* ns, const int32_t* ibas
   }
 }
 
+static spmv_status_t sell_fill(spmv_mat_s* src, spmv_mat_s* A, int64_t nunits, const int64_t* units, hipStream_t s) {
+  const unsigned gc = (unsigned)std::min<int64_t>(nunits, (int64_t)1 << 20);
+  if (A->dt == SPMV_F64)
+    k_csr_to_sell<double><<<gc, WAVE, 0, s>>>(src->M, nunits, A->C, src->ptr, src->col, (const double*)src->val,
+                                              A->perm, A->cs, units, A->scol, (double*)A->sval);
+  else
+    k_csr_to_sell<float><<<gc, WAVE, 0, s>>>(src->M, nunits, A->C, src->ptr, src->col, (const float*)src->val,
+                                             A->perm, A->cs, units, A->scol, (float*)A->sval);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
+}
+
 spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   const int64_t M = src->M;
   const int C = A->params.sell_C;
@@ -713,14 +734,23 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   SPMV_TRY(mat_alloc(A, (void**)&A->scol, sizeof(int32_t) * A->nslots));
   SPMV_TRY(mat_alloc(A, &A->sval, (size_t)A->sv * A->nslots));
   if (A->Mpad) {
-    const unsigned gc = (unsigned)std::min<int64_t>(A->nchunks, (int64_t)1 << 20);
-    if (A->dt == SPMV_F64)
-      k_csr_to_sell<double><<<gc, WAVE, 0, s>>>(M, A->nchunks, C, src->ptr, src->col, (const double*)src->val,
-                                                A->perm, A->cs, A->scol, (double*)A->sval);
-    else
-      k_csr_to_sell<float><<<gc, WAVE, 0, s>>>(M, A->nchunks, C, src->ptr, src->col, (const float*)src->val,
-                                               A->perm, A->cs, A->scol, (float*)A->sval);
-    SPMV_LAUNCH_CHECK();
+    SPMV_TRY(sell_fill(src, A, A->nchunks, nullptr, s));
+    if ((int64_t)maxlen * C > SELL_FILL) {  // the slots of long chunks beyond the first SELL_FILL
+      std::vector<int64_t> hcs(A->nchunks + 1), units;
+      SPMV_TRY(copy_to_host(hcs.data(), A->cs, sizeof(int64_t) * (A->nchunks + 1), s));
+      for (int64_t c = 0; c < A->nchunks; ++c)
+        for (int64_t q0 = SELL_FILL; q0 < hcs[c + 1] - hcs[c]; q0 += SELL_FILL) {
+          units.push_back(c);
+          units.push_back(q0);
+        }
+      if (!units.empty()) {
+        DTmp du;
+        SPMV_TRY(du.alloc(sizeof(int64_t) * units.size()));
+        SPMV_HIP(hipMemcpyAsync(du.p, units.data(), sizeof(int64_t) * units.size(), hipMemcpyHostToDevice, s));
+        SPMV_TRY(sell_fill(src, A, (int64_t)units.size() / 2, du.as<int64_t>(), s));
+        SPMV_HIP(hipStreamSynchronize(s));  // du and the host list are freed on return
+      }
+    }
   }
   // the narrow tail of the chunk list (one-pass kernel): not with C < 8 or
   // when the slice kernel is forced
