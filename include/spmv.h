@@ -92,7 +92,8 @@ typedef struct {
                                    eighth of x; per-band partial sums are added by a second pass */
 #define SPMV_FLAG_CSR_TILES 32u /* CSR: one wave per tile of 1,024 consecutive nonzeros (segmented scan in
                                    registers, no workgroup barrier), rows crossing tiles finished by an ordered
-                                   fix-up pass; for irregular rows.  Ignored with csr_lanes_per_row > 0 or bands */
+                                   fix-up pass; for irregular rows.  Ignored with csr_lanes_per_row > 0 or
+                                   SPMV_FLAG_CSR_BANDS; with bands > 1 each column band runs as tiles */
 
 typedef struct {
   int32_t fmt, dtype;
