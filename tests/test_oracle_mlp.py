@@ -84,3 +84,33 @@ def test_minmax_and_transform():
     # no clamping outside the training range
     out = oracle.minmax_apply(T[:1] * 0 + hi + (hi - lo), lo, hi)
     assert np.allclose(out[0][hi > lo], 2.0)
+
+
+def test_forward_by_hand():
+    # A two-sample network with hand-chosen weights, worked on paper; every value is exact in
+    # binary, so the comparison is exact.  Hidden unit 0 of layer 1 is cut by the ReLU for the
+    # second sample, unit 1 for the second sample as well; unit 0 of layer 2 for the first.
+    W1 = np.zeros((12, 64)); b1 = np.zeros(64)
+    W2 = np.zeros((64, 64)); b2 = np.zeros(64)
+    W3 = np.zeros((64, 5)); b3 = np.zeros(5)
+    W1[0, 0], W1[1, 0], b1[0] = 1.0, -2.0, 0.5      # a1_0 = x0 - 2 x1 + 0.5
+    W1[2, 1], b1[1] = 3.0, -1.0                      # a1_1 = 3 x2 - 1
+    W2[0, 0], W2[1, 0], b2[0] = 2.0, -5.0, 0.25      # a2_0 = 2 h1_0 - 5 h1_1 + 0.25
+    W2[0, 1], b2[1] = 1.0, -0.75                     # a2_1 = h1_0 - 0.75
+    b2[2] = 1.5                                      # a2_2 = 1.5
+    W3[0, 0] = 4.0                                   # z0 = 4 h2_0
+    W3[1, 1], b3[1] = 8.0, 0.5                       # z1 = 8 h2_1 + 0.5
+    W3[2, 2] = 2.0                                   # z2 = 2 h2_2
+    W3[2, 4], b3[4] = -1.0, -3.0                     # z4 = -h2_2 - 3
+    X = np.full((2, 12), 7.0)                        # features with zero weights still present
+    X[0, :3] = [1.0, 0.25, 0.5]
+    X[1, :3] = [0.0, 1.0, 0.0]
+    z, (_, a1, h1, a2, h2) = oracle.mlp_forward([W1, b1, W2, b2, W3, b3], X)
+    # sample 0: a1 = [1, 0.5]; a2 = [2 - 2.5 + 0.25, 1 - 0.75, 1.5] = [-0.25 (cut), 0.25, 1.5]
+    # sample 1: a1 = [-1.5, -1] (both cut); a2 = [0.25, -0.75 (cut), 1.5]
+    assert a1[:, :2].tolist() == [[1.0, 0.5], [-1.5, -1.0]]
+    assert h1[:, :2].tolist() == [[1.0, 0.5], [0.0, 0.0]]
+    assert a2[:, :3].tolist() == [[-0.25, 0.25, 1.5], [0.25, -0.75, 1.5]]
+    assert h2[:, :3].tolist() == [[0.0, 0.25, 1.5], [0.25, 0.0, 1.5]]
+    assert np.all(a1[:, 2:] == 0) and np.all(a2[:, 3:] == 0)
+    assert z.tolist() == [[0.0, 2.5, 3.0, 0.0, -4.5], [1.0, 0.5, 3.0, 0.0, -4.5]]

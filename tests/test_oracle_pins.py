@@ -409,3 +409,129 @@ def test_zipf_gini_matches_exact_distribution():
     f = oracle.features(A.M, A.N, A.ptr, A.col)
     assert abs(f[6] - 16.0) < 0.6 and f[5] <= 10_000 and f[4] >= 3
     assert abs(f[11] - 0.755) < 0.03
+
+
+# ------------------------------------------- pins of the remaining oracle parts
+
+def _brute_abs(M, N, ptr, col, val, x):
+    """Sum over row i of |a_ij * x_j| with python loops over the dense matrix."""
+    A = [[0.0] * N for _ in range(M)]
+    for i in range(M):
+        for k in range(ptr[i], ptr[i + 1]):
+            A[i][col[k]] += val[k]
+    return np.array([sum(abs(A[i][j] * x[j]) for j in range(N)) for i in range(M)])
+
+
+@pytest.mark.parametrize("idx", range(0, 39, 2))
+def test_absspmv_matches_brute_force(idx):
+    # the denominator of the row-wise error: mixed signs, so |sum| != sum of || unless the
+    # magnitudes are taken term by term; integer values make every sum exact
+    A = _cases()[idx]
+    rng = np.random.default_rng(100 + idx)
+    val = rng.integers(-8, 9, A.nnz).astype(float)
+    x = rng.integers(-8, 9, A.N).astype(float)
+    got = oracle.csr_absspmv(A.M, A.ptr, A.col, val, x)
+    assert np.array_equal(got, _brute_abs(A.M, A.N, A.ptr.tolist(), A.col.tolist(), val.tolist(), x.tolist()))
+    # never below the magnitude of the product itself
+    assert np.all(got >= np.abs(oracle.csr_spmv(A.M, A.ptr, A.col, val, x)))
+
+
+def test_absspmv_table1_by_hand():
+    # Table I's matrix with x = [1, -2, 3, -4]: rows 6*2 + 1*3, 2*1 + 8*3 + 3*4, 4*3, 7*2 + 5*3
+    ptr, col, val = t1()
+    x = np.array([1.0, -2.0, 3.0, -4.0])
+    assert oracle.csr_absspmv(4, ptr, col, val, x).tolist() == [15, 38, 12, 29]
+    assert oracle.csr_spmv(4, ptr, col, val, x).tolist() == [-9, 14, 12, 1]
+
+
+@pytest.mark.parametrize("idx", range(0, 39, 3))
+def test_spmm_columns_match_brute_force(idx):
+    # each column of Y = A X is the dense product of column c, integer-exact; the leading
+    # dimensions are wider than k, and the padding columns of Y are left untouched
+    import ctypes
+    A = _cases()[idx]
+    rng = np.random.default_rng(200 + idx)
+    val = rng.integers(-8, 9, A.nnz).astype(float)
+    k, ldx, ldy = 5, 7, 9
+    X = np.ascontiguousarray(rng.integers(-8, 9, (A.N, ldx)).astype(float))
+    Y = np.full((A.M, ldy), 12345.0)
+    L = oracle.lib()
+    ptr = np.ascontiguousarray(A.ptr, np.int32)
+    col = np.ascontiguousarray(A.col, np.int32)
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)  # noqa: E731
+    L.orc_csr_spmm(A.M, vp(ptr), vp(col), vp(val), k, vp(X), ldx, vp(Y), ldy)
+    for c in range(k):
+        want = brute(A.M, A.N, A.ptr.tolist(), A.col.tolist(), val.tolist(), X[:, c].tolist())
+        assert np.array_equal(Y[:, c], want), c
+        assert np.array_equal(Y[:, c], oracle.csr_spmv(A.M, A.ptr, A.col, val, np.ascontiguousarray(X[:, c])))
+    assert np.all(Y[:, k:] == 12345.0)
+    # the wrapper (ld = k) agrees
+    Xk = np.ascontiguousarray(X[:, :k])
+    assert np.array_equal(oracle.csr_spmm(A.M, A.ptr, A.col, val, Xk), Y[:, :k])
+
+
+def test_spmm_table1_by_hand():
+    # columns x = 1 and x = [1, 2, 3, 4] of Table I's matrix (row sums and the hand product)
+    ptr, col, val = t1()
+    X = np.array([[1.0, 1], [1, 2], [1, 3], [1, 4]])
+    assert oracle.csr_spmm(4, ptr, col, val, X).tolist() == [[7, 15], [13, 38], [4, 12], [12, 29]]
+
+
+@pytest.mark.parametrize("threads", [1, 2, 7])
+def test_threaded_oracle_loop_bit_identical(threads):
+    # the CPU-baseline loop: rows split over threads, each row still one sequential sum,
+    # so the result is the serial loop's bit for bit (non-integer values: rounding matters)
+    A = synth.zipf_rows(3000, 2500, seed=9, val_seed=10)
+    x = synth.vector(A.N, 11)
+    ptr, col = np.ascontiguousarray(A.ptr, np.int32), np.ascontiguousarray(A.col, np.int32)
+    val = np.ascontiguousarray(A.val, np.float64)
+    serial = oracle.csr_spmv(A.M, ptr, col, val, x)
+    y, used = oracle.csr_spmv_omp(A.M, ptr, col, val, x, threads)
+    assert used == threads
+    assert np.array_equal(y.view(np.uint64), serial.view(np.uint64))
+
+
+def _csr5_case(lens, w, s):
+    lens = np.asarray(lens)
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col = np.concatenate([np.arange(n) for n in lens]).astype(np.int32)
+    val = np.arange(1, ptr[-1] + 1, dtype=np.float64)
+    return ptr, col, val, oracle.csr_to_csr5(len(lens), ptr, col, val, w, s)
+
+
+def test_csr5_seg_off_hand_worked():
+    # Sec. II-B / Table I readings, worked by hand.  Rows of lengths 5 and 3, omega = sigma = 2:
+    # tile 0 holds entries 0-3 (lane 0: 0,1; lane 1: 2,3), tile 1 entries 4-7 (lane 0: 4,5;
+    # lane 1: 6,7).  Flags: entry 0 (row 0 starts), tile 1's first slot (forced, mid-row 0)
+    # and entry 5 (row 1 starts).  Lane 1 of each tile holds no flag, so lane 0 is followed by
+    # one flag-free lane.
+    ptr, col, val, c5 = _csr5_case([5, 3], 2, 2)
+    assert c5["tile_ptr"].tolist() == [0, 0, 2]
+    assert c5["bit_flag"].tolist() == [0b01, 0b00, 0b11, 0b00]
+    assert c5["y_off"].tolist() == [0, 1, 0, 2]
+    assert c5["seg_off"].tolist() == [1, 0, 1, 0]
+    # omega = 4, sigma = 2, rows of lengths 4 and 12: tile 0 flags lanes 0 (row 0) and 2
+    # (row 1 starts at entry 4); tile 1 (entries 8-15, all row 1) only its forced first slot
+    ptr, col, val, c5 = _csr5_case([4, 12], 4, 2)
+    assert c5["tile_ptr"].tolist() == [0, 1, 2]
+    assert c5["bit_flag"].tolist() == [1, 0, 1, 0, 1, 0, 0, 0]
+    assert c5["y_off"].tolist() == [0, 1, 1, 2, 0, 1, 1, 1]
+    assert c5["seg_off"].tolist() == [1, 0, 1, 0, 3, 2, 1, 0]
+    # Table I's own case is the all-zero one (every lane flagged)
+    ptr, col, val = t1()
+    assert oracle.csr_to_csr5(4, ptr, col, val, 2, 2)["seg_off"].tolist() == [0, 0, 0, 0]
+
+
+def test_csr5_seg_off_counts_flag_free_runs():
+    # on random layouts: seg_off[l] + 1 lanes from l reach the next flagged lane (or the tile's
+    # end), checked lane by lane from the flags alone
+    for seed in range(4):
+        A = synth.zipf_rows(300, 300, seed=20 + seed, val_seed=1)
+        for w, s in [(4, 2), (8, 3), (16, 4)]:
+            c5 = oracle.csr_to_csr5(A.M, A.ptr, A.col, A.val, w, s)
+            fl = c5["bit_flag"].reshape(-1, w)
+            so = c5["seg_off"].reshape(-1, w)
+            for t in range(fl.shape[0]):
+                for l in range(w):
+                    nxt = next((m for m in range(l + 1, w) if fl[t, m]), w)
+                    assert so[t, l] == nxt - l - 1
