@@ -167,14 +167,19 @@ void spmv_mat_free(spmv_mat_t A);
  * A's dtype. */
 spmv_status_t spmv_run(spmv_fmt_t fmt, spmv_mat_t A, const void* x, void* y, spmv_stream_t s);
 
-/* Y = A X for k right-hand sides, row-major: X[j*ldx + c], Y[i*ldy + c],
+/* Not in the paper: Sec. II-A's y = A x applied to k right-hand sides at once.
+ * Y = A X for k right-hand sides, row-major: X[j*ldx + c], Y[i*ldy + c],
  * c < k <= 64, ldx >= k, ldy >= k.  A must be a CSR handle
  * (SPMV_ERR_UNSUPPORTED otherwise); columns c >= k of Y are not touched. */
 spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t k, spmv_stream_t s);
 
-/* Batched launch: n CSR handles of one dtype processed by one persistent
- * kernel whose work list is balanced by nonzeros.  create builds the
- * device work list; run takes host arrays of n device pointers. */
+/* Not in the paper (it runs one matrix at a time; Sec. III-D splits one SpMV
+ * into tasks -- rows, block rows, tiles -- and this extends the tasks over many
+ * matrices).  Batched launch: n CSR handles of one dtype processed by ONE
+ * kernel launch, one workgroup per item of a work list built at creation (row
+ * blocks of every matrix, balanced by rows plus nonzeros); the hardware
+ * dispatcher hands out the items, so the grid is not persistent.  create
+ * builds the device work list; run takes host arrays of n device pointers. */
 spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* out);
 spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s);
 void spmv_batch_free(spmv_batch_t b);
@@ -182,7 +187,8 @@ void spmv_batch_free(spmv_batch_t b);
 /* ---------------------------------------------------------- measurement */
 
 /* Timed variants of spmv_run, spmv_spmm and spmv_batch_run (the byte and
- * time model of the measurements, Sec. IV-B).  start_event / stop_event are
+ * time model of the measurements: Sec. III-D, Alg. 1 times repeated runs
+ * and reports time and bandwidth).  start_event / stop_event are
  * hipEvent_t created by the caller (with timing enabled).  The call's first
  * kernel records start_event as it begins and its last kernel records
  * stop_event as it ends (the kernels are launched with hipExtLaunchKernel),
@@ -227,7 +233,8 @@ spmv_status_t spmv_copy_probe(int64_t bytes, int reps, spmv_stream_t s, double* 
 spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int reps, int64_t scrub_bytes,
                                 spmv_stream_t s, double* ms);
 
-/* Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: row
+/* Not in the paper (it fixes each format's parameters; Sec. II-B names them).
+ * Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: row
  * blocks, wave units, linear order, XCD bands, wave tiles, V lanes per row,
  * and, when x exceeds 4 MiB, row blocks and wave tiles over 2 and 4 column
  * bands; HYB: K in {rule, p50, p75, p90, p99}, each also with the COO tail

@@ -1,5 +1,6 @@
 """Matrix Market (coordinate) input, the file format of the paper's
-evaluation set (Sec. IV-A: matrices are read from files, then converted).
+evaluation set (Sec. III-D, Alg. 1: matrices are read from Matrix Market files
+into COO, then converted).
 
 Reads the `%%MatrixMarket matrix coordinate <field> <symmetry>` header with
 field real, integer or pattern and symmetry general, symmetric,

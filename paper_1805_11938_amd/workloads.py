@@ -9,11 +9,11 @@
   (seed 12), x seed 11.  Scale-free: ~56% empty rows, longest row ~3.7e5.
 
 They stand in for the regular and irregular matrices of the paper's
-evaluation (Sec. IV-A: square matrices with 10^5..2x10^7 nonzeros from
+evaluation (Sec. III-C: square matrices with 10^5..2x10^7 nonzeros from
 scientific and graph problems), which are not reproduced here.
 
 The launch configuration of each (workload, format) pair -- the parameters
-the benchmark converts with -- comes from the autotuner (Sec. III's tuning
+the benchmark converts with -- comes from the autotuner (Sec. II-B's tuning
 knobs: SELL chunk C and window sigma, CSR lanes per row, HYB width K, CSR5
 sigma) and is stored in ``data/tuned_params.json``; formats missing there use
 the library defaults.
