@@ -107,6 +107,11 @@ typedef struct {
 
 const char* spmv_status_str(spmv_status_t st);
 const char* spmv_last_error(void);
+/* Device bytes the library currently holds: live handles, batches, models and
+ * the workspaces it keeps (not the caller's buffers).  With the environment
+ * variable SPMV_MEM_CAP_BYTES set (read once per process), an allocation that
+ * would take this above the cap fails with SPMV_ERR_OOM. */
+int64_t spmv_mem_in_use(void);
 
 /* ------------------------------------------------------------ creation */
 
@@ -245,7 +250,8 @@ spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int r
  * column bands) on x/y and write the
  * fastest into *inout.  ms_out (optional) receives the best median.  The
  * result is cached for the life of the process, keyed by a 64-bit hash of
- * the sparsity structure (ptr, col), the shape, dtype, format and byte cap:
+ * the sparsity structure (ptr, col), the shape, dtype, format, byte cap and
+ * the caller's flags (the candidates keep the flags the grid does not set):
  * a second call for the same structure returns the cached choice without
  * timing (spmv_autotune_cache_clear empties the cache). */
 spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void* y, int64_t scrub_bytes, int reps,

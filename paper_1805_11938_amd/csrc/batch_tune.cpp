@@ -112,10 +112,13 @@ void spmv_batch_free(spmv_batch_t b) {
 // Exhaustive search over a small grid per format; each candidate is
 // converted and timed with the same protocol as spmv_time (median of the
 // confidence-interval rule).  Only performance depends on the choice.
-// Results are cached per (structure hash, shape, dtype, format, byte cap)
-// for the life of the process: tuning depends on the sparsity structure,
-// not on the values.
-typedef std::tuple<uint64_t, int64_t, int64_t, int64_t, int, int, int64_t> TuneKey;
+// Results are cached per (structure hash, shape, dtype, format, byte cap,
+// caller's flags) for the life of the process: tuning depends on the
+// sparsity structure, not on the values.  The flags are part of the key
+// because the candidates keep those the grid does not set (e.g.
+// SPMV_FLAG_SELL_SLICES), so callers asking for different flags are tuned
+// separately.
+typedef std::tuple<uint64_t, int64_t, int64_t, int64_t, int, int, int64_t, uint32_t> TuneKey;
 static std::mutex g_tune_mu;
 static std::map<TuneKey, std::pair<spmv_params_t, double>> g_tune_cache;
 
@@ -130,7 +133,7 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
   base.bands = 1;  // the candidates below set their own
   uint64_t h = 0;
   SPMV_TRY(structure_hash(csr, &h, st));
-  const TuneKey key(h, csr->M, csr->N, csr->nnz, (int)csr->dt, (int)fmt, base.max_bytes);
+  const TuneKey key(h, csr->M, csr->N, csr->nnz, (int)csr->dt, (int)fmt, base.max_bytes, base.flags);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);

@@ -91,6 +91,11 @@ void dfree(void* p) {
   (void)hipFree(p);
 }
 
+int64_t mem_in_use() {
+  std::lock_guard<std::mutex> g(g_mem_mu);
+  return g_live;
+}
+
 int64_t resident_blocks(int per_cu) {
   static int cus[64] = {0};
   int dev = 0;

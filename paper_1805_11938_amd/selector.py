@@ -58,13 +58,15 @@ def _to_device(A, dt):
     return S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt)
 
 
-def profile_matrix(Ad, x, y, reps_tune=3, scrub=SCRUB):
+def profile_matrix(Ad, x, y, reps_tune=3, scrub=SCRUB, max_bytes=None):
     """Autotune and time every format on one handle.  Returns
-    (times_ms[5], ci_ms[5], params per format)."""
+    (times_ms[5], ci_ms[5], params per format); a format refused by the byte
+    cap (max_bytes, default COLLECT_CAP) takes time +inf."""
     times, cis, params = [], [], {}
+    cap = COLLECT_CAP if max_bytes is None else max_bytes
     for f in CLASSES:
         try:
-            p, _ = Ad.autotune(f, x, y, scrub_bytes=scrub, reps=reps_tune, max_bytes=COLLECT_CAP)
+            p, _ = Ad.autotune(f, x, y, scrub_bytes=scrub, reps=reps_tune, max_bytes=cap)
             B = Ad.convert(f, **p)
             r = B.time(x, y, warmup=2, min_reps=20, max_reps=200, rel_ci=0.05, scrub_bytes=scrub)
             del B
@@ -297,33 +299,44 @@ def in_domain(Ad: "S.Matrix", model: "S.Model", tol: float = DOMAIN_TOL) -> bool
     return bool(np.all(X >= -tol) and np.all(X <= 1.0 + tol))
 
 
-def exhaustive(Ad, x, y):
+def exhaustive(Ad, x, y, max_bytes=None):
     """The fallback and judge: profile all five formats, return the fastest."""
-    times, _, params = profile_matrix(Ad, x, y)
+    times, _, params = profile_matrix(Ad, x, y, max_bytes=max_bytes)
     f = label_of(times)
     return CLASSES[f], params[CLASSES[f]], times
 
 
-def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB):
+REFUSED = (-4, -5)  # too large for the byte cap, or a combination the kernels do not implement
+
+
+def auto(Ad, x, y, model=None, margin=0.0, tune=True, scrub=SCRUB, max_bytes=None):
     """Pick a format and its parameters for a CSR handle and return the
     converted handle with how it was chosen.
 
     With a model: predicted format, then (tune=True) the autotuner's
     parameters for it.  Without a model, when the matrix's features lie
-    outside the model's training range (in_domain), or when the model's top
-    softmax probability beats the runner-up by less than `margin`, every
+    outside the model's training range (in_domain), when the model's top
+    softmax probability beats the runner-up by less than `margin`, or when
+    the predicted format cannot hold the matrix (e.g. ELL above the byte cap
+    max_bytes, default COLLECT_CAP: the training labels give such formats
+    time +inf, but nothing stops the network from predicting one), every
     format is profiled and the fastest is taken (the exhaustive fallback)."""
+    cap = COLLECT_CAP if max_bytes is None else max_bytes
     if model is not None and in_domain(Ad, model):
         fmt, z = choose(Ad, model)
         p = np.exp(z - z.max())
         p = np.sort(p / p.sum())[::-1]
         if p[0] - p[1] >= margin:
-            params = {}
-            if tune:
-                params, _ = Ad.autotune(fmt, x, y, scrub_bytes=scrub, reps=3)
-            return Ad.convert(fmt, **params), fmt, "model"
-    fmt, params, _ = exhaustive(Ad, x, y)
-    return Ad.convert(fmt, **(params or {})), fmt, "exhaustive"
+            try:
+                params = {"max_bytes": cap}
+                if tune:
+                    params, _ = Ad.autotune(fmt, x, y, scrub_bytes=scrub, reps=3, max_bytes=cap)
+                return Ad.convert(fmt, **params), fmt, "model"
+            except S.SpmvError as e:
+                if e.status not in REFUSED:
+                    raise
+    fmt, params, _ = exhaustive(Ad, x, y, max_bytes=cap)
+    return Ad.convert(fmt, **dict(params or {}, max_bytes=cap)), fmt, "exhaustive"
 
 
 def worth_converting(t_convert_ms, t_csr_ms, t_fmt_ms, calls):
@@ -343,7 +356,12 @@ def auto_for_calls(Ad, x, y, model, calls, scrub=SCRUB):
         return Ad, "csr", {"reason": "model chose csr"}
     e0, e1 = S.timing_events()
     e0.record()
-    B = Ad.convert(fmt)
+    try:
+        B = Ad.convert(fmt, max_bytes=COLLECT_CAP)
+    except S.SpmvError as e:
+        if e.status not in REFUSED:
+            raise
+        return Ad, "csr", {"reason": f"model chose {fmt}, which cannot hold this matrix ({e})"}
     e1.record()
     torch.cuda.synchronize()
     t_conv = e0.elapsed_time(e1)
