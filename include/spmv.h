@@ -297,6 +297,20 @@ spmv_status_t spmv_mlp_backward(const float* params, const float* X, const int32
                                 float* grads, float* loss, spmv_stream_t s);
 spmv_status_t spmv_mlp_adam(float* params, const float* grads, float* m, float* v, int32_t t, float lr, float beta1,
                             float beta2, float eps, spmv_stream_t s);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * spmv_mlp_backward without any allocation.  Same arguments, kernels and
+ * results as spmv_mlp_backward, but its scratch (activations, deltas and
+ * per-sample losses of up to SPMV_NOALLOC_MAX_BATCH samples, 4.3 MB) is one
+ * static array in the library's device code, which each GPU holds from the
+ * first call on it until the process ends.  B > SPMV_NOALLOC_MAX_BATCH ->
+ * SPMV_ERR_TOO_LARGE.  Only enqueues work on s (no synchronisation), so grads
+ * and loss are ready when s reaches this point.  Every call on one GPU shares
+ * that GPU's scratch: calls that may overlap on one GPU (different streams,
+ * or host threads) race and must be serialised by the caller. */
+#define SPMV_NOALLOC_MAX_BATCH 4096
+spmv_status_t spmv_mlp_backward_noalloc(const float* params, const float* X, const int32_t* labels, int32_t B,
+                                        float* grads, float* loss, spmv_stream_t s);
 /* Feature transform + min-max scaling on the device: F (n x 12 FP64 raw
  * features) -> X (n x 12 FP32 scaled).  fmin/fmax: host arrays. */
 spmv_status_t spmv_scale_features(const double* F, int32_t n, const double fmin[12], const double fmax[12],

@@ -493,6 +493,11 @@ __global__ void k_gather_batch(const float* __restrict__ X, const int32_t* __res
   if (k == 0) yb[r] = labels[src];
 }
 
+// Scratch of the backward pass: activations, deltas and per-sample losses.
+struct BwdPtrs {
+  float *h1, *h2, *dz, *da1, *da2, *loss;
+};
+
 struct BwdBuf {
   DTmp h1, h2, dz, da1, da2, loss;
   spmv_status_t alloc(int32_t B) {
@@ -504,20 +509,53 @@ struct BwdBuf {
     SPMV_TRY(loss.alloc(sizeof(float) * B));
     return SPMV_OK;
   }
+  BwdPtrs ptrs() const {
+    return {h1.as<float>(), h2.as<float>(), dz.as<float>(), da1.as<float>(), da2.as<float>(), loss.as<float>()};
+  }
 };
+
+// The backward scratch of spmv_mlp_backward_noalloc: the six buffers of
+// BwdBuf for SPMV_NOALLOC_MAX_BATCH samples, at fixed offsets, in one array
+// that the code object carries (each GPU holds its own copy for the life of
+// the process).  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+constexpr int64_t NA_B = SPMV_NOALLOC_MAX_BATCH;
+constexpr int64_t NA_H1 = 0, NA_H2 = NA_H1 + NA_B * NH, NA_DZ = NA_H2 + NA_B * NH, NA_DA1 = NA_DZ + NA_B * NOUT,
+                  NA_DA2 = NA_DA1 + NA_B * NH, NA_LOSS = NA_DA2 + NA_B * NH, NA_FLOATS = NA_LOSS + NA_B;
+static __device__ __align__(256) float scratch[NA_FLOATS];
+
+static std::mutex g_na_mu;
+static float* g_na_ptr[64] = {nullptr};  // per device: the device address of scratch
+
+static spmv_status_t noalloc_scratch(BwdPtrs* out) {
+  int dev = -1;
+  SPMV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(SPMV_ERR_UNSUPPORTED, "device %d (at most 64 devices)", dev);
+  std::lock_guard<std::mutex> g(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(SPMV_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    }
+    g_na_ptr[dev] = (float*)p;
+  }
+  float* b = g_na_ptr[dev];
+  *out = {b + NA_H1, b + NA_H2, b + NA_DZ, b + NA_DA1, b + NA_DA2, b + NA_LOSS};
+  return SPMV_OK;
+}
 
 static unsigned waves_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4), 4096)); }
 
 static spmv_status_t backward(const float* P, const float* X, const int32_t* labels, int32_t B, float* G,
-                              float* loss_out, float* loss_acc, float weight, BwdBuf& w, hipStream_t s) {
-  k_mlp_delta<<<waves_grid(B), BS, 0, s>>>(P, X, labels, B, w.h1.as<float>(), w.h2.as<float>(), w.dz.as<float>(),
-                                           w.da1.as<float>(), w.da2.as<float>(), w.loss.as<float>());
+                              float* loss_out, float* loss_acc, float weight, const BwdPtrs& w, hipStream_t s) {
+  k_mlp_delta<<<waves_grid(B), BS, 0, s>>>(P, X, labels, B, w.h1, w.h2, w.dz, w.da1, w.da2, w.loss);
   SPMV_LAUNCH_CHECK();
-  k_mlp_wgrad<<<(unsigned)cdiv(NPARAM, BS), BS, 0, s>>>(X, w.h1.as<float>(), w.h2.as<float>(), w.dz.as<float>(),
-                                                         w.da1.as<float>(), w.da2.as<float>(), B, G);
+  k_mlp_wgrad<<<(unsigned)cdiv(NPARAM, BS), BS, 0, s>>>(X, w.h1, w.h2, w.dz, w.da1, w.da2, B, G);
   SPMV_LAUNCH_CHECK();
   if (loss_out || loss_acc) {
-    k_mean<<<1, 1, 0, s>>>(w.loss.as<float>(), B, loss_out, loss_acc, weight);
+    k_mean<<<1, 1, 0, s>>>(w.loss, B, loss_out, loss_acc, weight);
     SPMV_LAUNCH_CHECK();
   }
   return SPMV_OK;
@@ -549,9 +587,22 @@ spmv_status_t spmv_mlp_backward(const float* params, const float* X, const int32
   if (!params || !X || !labels || !grads || B <= 0) return fail(SPMV_ERR_INVALID_ARG, "backward arguments");
   BwdBuf w;
   SPMV_TRY(w.alloc(B));
-  SPMV_TRY(backward(params, X, labels, B, grads, loss, nullptr, 0.0f, w, hs(s)));
+  SPMV_TRY(backward(params, X, labels, B, grads, loss, nullptr, 0.0f, w.ptrs(), hs(s)));
   SPMV_HIP(hipStreamSynchronize(hs(s)));
   return SPMV_OK;
+}
+
+spmv_status_t spmv_mlp_backward_noalloc(const float* params, const float* X, const int32_t* labels, int32_t B,
+                                        float* grads, float* loss, spmv_stream_t s) {
+  if (!params || !X || !labels || !grads || B <= 0) return fail(SPMV_ERR_INVALID_ARG, "backward arguments");
+  if (B > SPMV_NOALLOC_MAX_BATCH)
+    return fail(SPMV_ERR_TOO_LARGE, "batch of %d samples (the allocation-free backward takes at most %d)", (int)B,
+                SPMV_NOALLOC_MAX_BATCH);
+  BwdPtrs w;
+  SPMV_TRY(noalloc_scratch(&w));
+  // every scratch element the kernels read is written first by this call's
+  // k_mlp_delta, so nothing needs clearing
+  return backward(params, X, labels, B, grads, loss, nullptr, 0.0f, w, hs(s));
 }
 
 spmv_status_t spmv_mlp_adam(float* params, const float* grads, float* m, float* v, int32_t t, float lr, float beta1,
@@ -615,7 +666,7 @@ spmv_status_t spmv_mlp_train(float* params, const float* X, const int32_t* label
                                                                    Xb.as<float>(), yb.as<int32_t>());
       SPMV_LAUNCH_CHECK();
       SPMV_TRY(backward(params, Xb.as<float>(), yb.as<int32_t>(), nb, G.as<float>(), nullptr,
-                        eloss.as<float>() + e, (float)nb / (float)n, w, st));
+                        eloss.as<float>() + e, (float)nb / (float)n, w.ptrs(), st));
       ++t;
       k_adam<<<(unsigned)cdiv(NPARAM, BS), BS, 0, st>>>(params, G.as<float>(), m.as<float>(), v.as<float>(), t, lr,
                                                           0.9f, 0.999f, 1e-8f);

@@ -20,6 +20,7 @@ FMT = {"csr": 0, "csr5": 1, "ell": 2, "sell": 3, "hyb": 4}
 FMT_NAMES = ("csr", "csr5", "ell", "sell", "hyb")
 F64, F32 = 0, 1
 NPARAM = 5317
+NOALLOC_MAX_BATCH = 4096  # SPMV_NOALLOC_MAX_BATCH
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "bad structure", -3: "out of memory", -4: "too large",
           -5: "unsupported", -6: "HIP error", -7: "model error"}
@@ -62,7 +63,7 @@ EXPORTED = [
     "spmv_autotune", "spmv_features", "spmv_model_create", "spmv_model_load", "spmv_model_save",
     "spmv_model_params", "spmv_model_free", "spmv_select", "spmv_mlp_forward", "spmv_mlp_backward", "spmv_mlp_adam",
     "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train", "spmv_run_timed", "spmv_spmm_timed",
-    "spmv_batch_run_timed", "spmv_autotune_cache_clear", "spmv_mem_in_use",
+    "spmv_batch_run_timed", "spmv_autotune_cache_clear", "spmv_mem_in_use", "spmv_mlp_backward_noalloc",
 ]
 
 _L = None
@@ -111,6 +112,7 @@ def lib():
             "spmv_select": (st, [vp, vp, ctypes.POINTER(st), vp]),
             "spmv_mlp_forward": (st, [vp, vp, i32, vp, vp, vp, vp]),
             "spmv_mlp_backward": (st, [vp, vp, vp, i32, vp, vp, vp]),
+            "spmv_mlp_backward_noalloc": (st, [vp, vp, vp, i32, vp, vp, vp]),
             "spmv_mlp_adam": (st, [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, vp]),
             "spmv_scale_features": (st, [vp, i32, vp, vp, vp, vp]),
