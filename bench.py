@@ -53,26 +53,57 @@ def build_workload(names):
     return out
 
 
-def cpu_baseline(work, sv, budget_s=15.0):
-    """The oracle's FP64 CSR loop, OpenMP rows over the host cores (FP32
-    values are promoted, so its bytes are counted at the FP64 size)."""
-    import oracle
-    threads = min(os.cpu_count() or 1, 16)
-    tot_bytes, tot_t, reps, used = 0.0, 0.0, 0, 1
+def _ci_timed(fn, min_s, budget_s, min_reps=20, max_reps=1000, rel_ci=0.025):
+    """Times of fn() repeated for at least min_s seconds and min_reps runs,
+    until the 95% confidence interval of the mean is within +-rel_ci of it,
+    at most max_reps runs or budget_s seconds.  Returns (times in s, CI
+    half-width / mean)."""
+    fn()  # warm-up
+    ts = []
     t_start = time.time()
-    while time.time() - t_start < budget_s or reps < 2:
-        for name, M, ptr, col, val, x in work:
-            t0 = time.perf_counter()
-            _, used = oracle.csr_spmv_omp(M, ptr, col, val, x, threads)
-            tot_t += time.perf_counter() - t0
-            tot_bytes += len(col) * 12 + 4 * (M + 1) + 8 * len(x) + 8 * M
-        reps += 1
-        if reps >= 20000:
-            break
-    return {"value": round(tot_bytes / tot_t / 1e9, 3), "unit": "GB/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{reps} passes of y=Ax over every matrix of the workload in full (FP64 CSR loop, "
-                      f"OpenMP static rows), about {budget_s:.0f} s",
-            "ms_per_step": round(1e3 * tot_t / reps, 3)}
+    while len(ts) < max_reps:
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+        el = time.time() - t_start
+        if len(ts) >= min_reps and el >= min_s:
+            a = np.asarray(ts)
+            rel = 1.96 * a.std(ddof=1) / np.sqrt(len(a)) / a.mean()
+            if rel <= rel_ci or el > budget_s:
+                return ts, float(rel)
+    a = np.asarray(ts)
+    return ts, float(1.96 * a.std(ddof=1) / np.sqrt(len(a)) / a.mean())
+
+
+def cpu_baseline(work, sv, min_s=6.0, budget_s=15.0):
+    """The oracle's FP64 CSR loop on the same matrices (FP32 values are
+    promoted, so its bytes are counted at the FP64 size): OpenMP static rows
+    over the host cores this process may use (at most 16: the CPU share of a
+    one-GPU machine), and single-threaded.  One pass = y = A x over every matrix of
+    the workload; passes repeat for at least min_s seconds each way, then
+    under the timing rule (95% CI of the mean within 2.5%, 20..1000 passes,
+    or the time budget)."""
+    import oracle
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(avail, 16))
+    nbytes = sum(len(col) * 12 + 4 * (M + 1) + 8 * len(x) + 8 * M for _, M, ptr, col, val, x in work)
+    used = [1]
+
+    def one_pass(nt):
+        for _, M, ptr, col, val, x in work:
+            _, used[0] = oracle.csr_spmv_omp(M, ptr, col, val, x, nt)
+
+    ts, rel = _ci_timed(lambda: one_pass(threads), min_s, budget_s)
+    cores = int(used[0])
+    ts1, rel1 = _ci_timed(lambda: one_pass(1), min_s, budget_s)
+    med, med1 = float(np.median(ts)), float(np.median(ts1))
+    return {"value": round(nbytes / med / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(ts)} passes of y=Ax over every matrix of the workload in full (FP64 CSR loop, "
+                      f"OpenMP static rows over {cores} threads), median pass; 95% CI +-{100 * rel:.1f}%",
+            "ms_per_step": round(1e3 * med, 3), "ci_rel": round(rel, 4), "reps": len(ts),
+            "host_cpus": os.cpu_count(), "cpus_available": avail,
+            "single_thread": {"value": round(nbytes / med1 / 1e9, 3), "unit": "GB/s", "ms_per_step": round(1e3 * med1, 3),
+                              "reps": len(ts1), "ci_rel": round(rel1, 4)}}
 
 
 WORKLOADS = {"c2": ("stencil27_100", "zipf_1M"), "rmat24": ("rmat24",)}

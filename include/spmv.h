@@ -94,6 +94,9 @@ typedef struct {
                                    registers, no workgroup barrier), rows crossing tiles finished by an ordered
                                    fix-up pass; for irregular rows.  Ignored with csr_lanes_per_row > 0 or
                                    SPMV_FLAG_CSR_BANDS; with bands > 1 each column band runs as tiles */
+#define SPMV_FLAG_SPLIT4 64u    /* ELL with K <= 32 and SELL chunks of C = 64 at most 32 wide: four waves share
+                                  each 64 rows, each taking a quarter of every row's slots; the four sums are
+                                  added in wave order (fewer registers per wave, more loads in flight per CU) */
 
 typedef struct {
   int32_t fmt, dtype;
@@ -239,16 +242,18 @@ spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int r
                                 spmv_stream_t s, double* ms);
 
 /* Not in the paper (it fixes each format's parameters; Sec. II-B names them).
- * Autotuner: time every candidate of fmt's grid (SELL: C x sigma; CSR: row
- * blocks, wave units, linear order, XCD bands, wave tiles, V lanes per row,
- * and, when x exceeds 4 MiB, row blocks and wave tiles over 2 and 4 column
- * bands; HYB: K in {rule, p50, p75, p90, p99}, each also with the COO tail
- * over 2 and 4 column bands when x exceeds 4 MiB (and 8 above 32 MiB);
- * CSR5: sigma; SELL sigma in
- * {1, C, 8C, 256C, M}, M being one window over all rows, and, when x exceeds
- * 8 MiB, column bands of at most 8 MiB of x with sigma = M; CSR5: also such
- * column bands) on x/y and write the
- * fastest into *inout.  ms_out (optional) receives the best median.  The
+ * Autotuner: time every candidate of fmt's grid on x/y and write the
+ * fastest into *inout.  CSR: row blocks, wave units, linear order, XCD
+ * bands, wave tiles, V lanes per row, and, when x exceeds 4 MiB, row blocks
+ * and wave tiles over 2 and 4 column bands.  CSR5: sigma in {4, 8, 16, 32};
+ * when x exceeds 4 MiB also sigma 16 and 32 over 2 and 4 column bands (8 too
+ * above 32 MiB).  ELL: one wave or four waves per 64 rows.  SELL: C in {8,
+ * 16, 32, 64} x sigma in {1, C, 8C, 256C, M} (M: one window over all rows),
+ * C = 64 also with four waves per chunk, and, when x exceeds 4 MiB, C 32 and
+ * 64 with sigma = M over 2 and 4 column bands (8 above 32 MiB).  HYB: K in
+ * {rule, p50, p75, p90, p99}, each with one or four waves per 64 rows of the
+ * ELL part and with the COO tail over 2 and 4 column bands when x exceeds
+ * 4 MiB (8 above 32 MiB).  ms_out (optional) receives the best median.  The
  * result is cached for the life of the process, keyed by a 64-bit hash of
  * the sparsity structure (ptr, col), the shape, dtype, format, byte cap and
  * the caller's flags (the candidates keep the flags the grid does not set):

@@ -143,16 +143,16 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       return SPMV_OK;
     }
   }
-  // x larger than 8 MiB: column bands holding at most 8 MiB of x each (at
-  // most 8) are candidates too.  Random gathers from a slice that fits the
-  // L2s cost about half those served from the Infinity Cache, but each band
-  // adds launches and an M-long partial product; measured, bands paid off
-  // from about 16 MB of x on and not at 8 MB.
-  int xbands = 1;
+  // x larger than one XCD's 4 MiB L2: SELL and CSR5 over 2 and 4 column
+  // bands (8 too above 32 MiB) are candidates.  Random gathers from a slice
+  // that fits the L2s cost about half those served from the Infinity Cache,
+  // but each band adds launches and an M-long partial product; measured,
+  // they paid off on x of 16 MB and more, not at 8 MB.
+  std::vector<int> xbands;
   {
-    const int64_t xb = csr->N * (int64_t)csr->sv, slice = (int64_t)8 << 20;
-    while (xbands < 8 && xb > slice * xbands) xbands *= 2;
-    if (csr->M == 0) xbands = 1;
+    const int64_t xb = csr->N * (int64_t)csr->sv;
+    if (csr->M && xb > ((int64_t)4 << 20)) xbands = {2, 4};
+    if (csr->M && xb > ((int64_t)32 << 20)) xbands.push_back(8);
   }
   std::vector<spmv_params_t> cand;
   auto add = [&](auto&& f) {
@@ -192,12 +192,13 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       break;
     case SPMV_FMT_CSR5:
       for (int sg : {4, 8, 16, 32}) add([sg](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = 1; });
-      if (xbands > 1)
+      for (int nb : xbands)
         for (int sg : {16, 32})
-          add([sg, xbands](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = xbands; });
+          add([sg, nb](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = nb; });
       break;
     case SPMV_FMT_ELL:
-      add([](spmv_params_t&) {});
+      add([](spmv_params_t& p) { p.flags &= ~SPMV_FLAG_SPLIT4; });
+      add([](spmv_params_t& p) { p.flags |= SPMV_FLAG_SPLIT4; });
       break;
     case SPMV_FMT_SELL:
       // sigma in {1, C, 8C, 256C} and one window over all rows (a global
@@ -206,13 +207,32 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
         const int64_t all = std::max<int64_t>(csr->M, 1);
         for (int64_t sg : {(int64_t)1, (int64_t)C, (int64_t)8 * C, (int64_t)256 * C, all}) {
           if (sg == all && all <= (int64_t)256 * C) continue;  // 256C already covers every row
-          add([C, sg](spmv_params_t& p) { p.sell_C = C; p.sell_sigma = (int32_t)sg; p.bands = 1; });
+          add([C, sg](spmv_params_t& p) {
+            p.sell_C = C;
+            p.sell_sigma = (int32_t)sg;
+            p.bands = 1;
+            p.flags &= ~SPMV_FLAG_SPLIT4;
+          });
+          // C = 64: also four waves per chunk
+          if (C == 64)
+            add([C, sg](spmv_params_t& p) {
+              p.sell_C = C;
+              p.sell_sigma = (int32_t)sg;
+              p.bands = 1;
+              p.flags |= SPMV_FLAG_SPLIT4;
+            });
         }
       }
-      if (xbands > 1) {
+      if (!xbands.empty()) {
         const int32_t all = (int32_t)std::min<int64_t>(csr->M, INT32_MAX);
-        for (int C : {32, 64})
-          add([C, all, xbands](spmv_params_t& p) { p.sell_C = C; p.sell_sigma = all; p.bands = xbands; });
+        for (int nb : xbands)
+          for (int C : {32, 64})
+            add([C, all, nb](spmv_params_t& p) {
+              p.sell_C = C;
+              p.sell_sigma = all;
+              p.bands = nb;
+              p.flags &= ~SPMV_FLAG_SPLIT4;
+            });
       }
       break;
     case SPMV_FMT_HYB: {
@@ -237,7 +257,13 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       if (csr->M && xbytes > ((int64_t)4 << 20)) nbs.insert(nbs.end(), {2, 4});
       if (csr->M && xbytes > ((int64_t)32 << 20)) nbs.push_back(8);
       for (int nb : nbs)
-        for (int32_t K : Ks) add([K, nb](spmv_params_t& p) { p.hyb_K = K; p.bands = nb; });
+        for (int32_t K : Ks)
+          for (uint32_t sp : {0u, (uint32_t)SPMV_FLAG_SPLIT4})
+            add([K, nb, sp](spmv_params_t& p) {
+              p.hyb_K = K;
+              p.bands = nb;
+              p.flags = (p.flags & ~SPMV_FLAG_SPLIT4) | sp;
+            });
       break;
     }
     default: return fail(SPMV_ERR_INVALID_ARG, "format %d", (int)fmt);

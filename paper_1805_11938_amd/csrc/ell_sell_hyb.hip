@@ -192,6 +192,83 @@ __global__ __launch_bounds__(WAVE) void k_ell_kc(int64_t M, const int32_t* __res
   y[i] = (T)((s[0] + s[1]) + (s[2] + s[3]));
 }
 
+// Narrow ELL, four waves per 64 rows: wave h takes the slots [h*q, min(K,
+// (h+1)*q)), q = ceil(K/4); the four sums are added in wave order in LDS.
+template <typename T, int KC>
+__global__ __launch_bounds__(4 * WAVE) void k_ell_kc4(int64_t M, const int32_t* __restrict__ ecol,
+                                                     const T* __restrict__ eval, const T* __restrict__ x,
+                                                     T* __restrict__ y, int xcd) {
+  constexpr int KQ = (KC + 3) / 4;
+  __shared__ double part[4][WAVE];
+  const int h = (int)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  const int p = (int)(threadIdx.x & (WAVE - 1));
+  const int64_t i = (int64_t)(xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * WAVE + p;
+  const int k0 = h * KQ;
+  constexpr int NLAST = KC - 3 * KQ;  // slots of the last wave (may be < KQ, or <= 0)
+  const int n = h < 3 ? (KQ < KC - k0 ? KQ : KC - k0) : NLAST;
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < M && n > 0) {
+    int32_t c[KQ];
+    T v[KQ], xv[KQ];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) c[u] = u < n ? ldnt32(ecol + (int64_t)(k0 + u) * M, (uint32_t)i) : -1;
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) v[u] = u < n ? ldnt32(eval + (int64_t)(k0 + u) * M, (uint32_t)i) : (T)0;
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) xv[u] = ld32(x, (uint32_t)(c[u] >= 0 ? c[u] : 0));
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) sa[u & 3] += c[u] >= 0 ? (double)v[u] * (double)xv[u] : 0.0;
+  }
+  part[h][p] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+  __syncthreads();
+  if (h == 0 && i < M) y[i] = (T)(((part[0][p] + part[1][p]) + part[2][p]) + part[3][p]);
+}
+
+template <typename T>
+static void launch_ell_kc4(int64_t M, int32_t k, const int32_t* ecol, const void* eval, const void* x, void* y,
+                           unsigned g, int xcd, hipStream_t s) {
+  const T* ev = (const T*)eval;
+  const T* xv = (const T*)x;
+  T* yv = (T*)y;
+  switch (k) {
+    case 1: launch(k_ell_kc4<T, 1>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 2: launch(k_ell_kc4<T, 2>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 3: launch(k_ell_kc4<T, 3>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 4: launch(k_ell_kc4<T, 4>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 5: launch(k_ell_kc4<T, 5>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 6: launch(k_ell_kc4<T, 6>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 7: launch(k_ell_kc4<T, 7>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 8: launch(k_ell_kc4<T, 8>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 9: launch(k_ell_kc4<T, 9>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 10: launch(k_ell_kc4<T, 10>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 11: launch(k_ell_kc4<T, 11>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 12: launch(k_ell_kc4<T, 12>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 13: launch(k_ell_kc4<T, 13>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 14: launch(k_ell_kc4<T, 14>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 15: launch(k_ell_kc4<T, 15>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 16: launch(k_ell_kc4<T, 16>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 17: launch(k_ell_kc4<T, 17>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 18: launch(k_ell_kc4<T, 18>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 19: launch(k_ell_kc4<T, 19>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 20: launch(k_ell_kc4<T, 20>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 21: launch(k_ell_kc4<T, 21>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 22: launch(k_ell_kc4<T, 22>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 23: launch(k_ell_kc4<T, 23>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 24: launch(k_ell_kc4<T, 24>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 25: launch(k_ell_kc4<T, 25>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 26: launch(k_ell_kc4<T, 26>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 27: launch(k_ell_kc4<T, 27>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 28: launch(k_ell_kc4<T, 28>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 29: launch(k_ell_kc4<T, 29>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 30: launch(k_ell_kc4<T, 30>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 31: launch(k_ell_kc4<T, 31>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    case 32: launch(k_ell_kc4<T, 32>, g, 4 * WAVE, s, M, ecol, ev, xv, yv, xcd); break;
+    default: break;
+  }
+}
+
 template <typename T, bool XCD>
 static void launch_ell_kc(int64_t M, int32_t k, const int32_t* ecol, const void* eval, const void* x, void* y,
                           unsigned g, hipStream_t s) {
@@ -234,12 +311,14 @@ static void launch_ell_kc(int64_t M, int32_t k, const int32_t* ecol, const void*
 
 template <typename T>
 static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const void* eval, const void* x, void* y,
-                                bool xcd, hipStream_t s) {
+                                bool xcd, bool split4, hipStream_t s) {
   if (M == 0) return SPMV_OK;
   if (K >= 1 && K <= 32) {
-    const unsigned g = (unsigned)cdiv(M, WAVE);  // one wave per workgroup
+    const unsigned g = (unsigned)cdiv(M, WAVE);  // one workgroup per 64 rows
     const int32_t k = (int32_t)K;
-    if (xcd)
+    if (split4)
+      launch_ell_kc4<T>(M, k, ecol, eval, x, y, g, xcd ? 1 : 0, s);
+    else if (xcd)
       launch_ell_kc<T, true>(M, k, ecol, eval, x, y, g, s);
     else
       launch_ell_kc<T, false>(M, k, ecol, eval, x, y, g, s);
@@ -260,8 +339,9 @@ static spmv_status_t launch_ell(int64_t M, int64_t K, const int32_t* ecol, const
 
 spmv_status_t run_ell(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   const bool xcd = !(A->params.flags & SPMV_FLAG_LINEAR);
-  if (A->dt == SPMV_F64) return launch_ell<double>(A->M, A->K, A->ecol, A->eval, x, y, xcd, s);
-  return launch_ell<float>(A->M, A->K, A->ecol, A->eval, x, y, xcd, s);
+  const bool split4 = (A->params.flags & SPMV_FLAG_SPLIT4) != 0;
+  if (A->dt == SPMV_F64) return launch_ell<double>(A->M, A->K, A->ecol, A->eval, x, y, xcd, split4, s);
+  return launch_ell<float>(A->M, A->K, A->ecol, A->eval, x, y, xcd, split4, s);
 }
 
 static spmv_status_t check_cap(const spmv_mat_s* A, int64_t bytes, const char* what) {
@@ -516,6 +596,45 @@ __global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t c0, int64_t
   if (r >= 0) y[r] = (T)((sa[0] + sa[1]) + (sa[2] + sa[3]));
 }
 
+// Narrow SELL with C = 64, four waves per chunk: wave h takes the slots
+// [h*q, min(w, (h+1)*q)) of each stored row, q = ceil(w/4), with every one of
+// its loads in flight; the four sums are added in wave order through LDS.
+// Against one wave per chunk this holds a quarter of the registers per wave
+// (twice the waves per SIMD) and a quarter of the dependent round trip per
+// wave, so the chunk streams keep more bytes in flight.
+template <typename T, bool PERM, int KC>
+__global__ __launch_bounds__(4 * WAVE) void k_sell_kc4(int64_t M, int64_t c0, int64_t nchunks,
+                                                      const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ scol, const T* __restrict__ sval,
+                                                      const T* __restrict__ x, T* __restrict__ y, int remap) {
+  constexpr int KQ = (KC + 3) / 4;
+  __shared__ double part[4][WAVE];
+  const int h = (int)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  const int p = (int)(threadIdx.x & (WAVE - 1));
+  const int64_t c = c0 + (int64_t)(remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
+  if (c >= nchunks) return;  // uniform over the workgroup
+  const int64_t base = cs[c];
+  const int w = (int)((cs[c + 1] - base) >> 6);
+  const int q = (w + 3) >> 2;
+  const int k0 = h * q;
+  const int n = w - k0 < q ? w - k0 : q;  // this wave's slots (may be <= 0)
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  if (n > 0) {
+    const int32_t* cc = scol + base + (int64_t)k0 * WAVE + p;
+    const T* vv = sval + base + (int64_t)k0 * WAVE + p;
+    if (KQ > 4 && n > 4) sell_slots<T, 6, KQ>(cc, vv, x, n, sa);
+    else if (KQ > 2 && n > 2) sell_slots<T, 6, (KQ < 4 ? KQ : 4)>(cc, vv, x, n, sa);
+    else sell_slots<T, 6, (KQ < 2 ? KQ : 2)>(cc, vv, x, n, sa);
+  }
+  part[h][p] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+  __syncthreads();
+  if (h == 0) {
+    const int64_t pos = c * WAVE + p;
+    const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+    if (r >= 0) y[r] = (T)(((part[0][p] + part[1][p]) + part[2][p]) + part[3][p]);
+  }
+}
+
 // one thread per (wide chunk, stored row): y = sum of the slices' partials in order
 template <typename T, bool PERM>
 __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restrict__ wide,
@@ -550,6 +669,15 @@ static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s)
   // contiguous ranges per XCD only while a sort window is small next to an
   // XCD's share of the rows (chunk widths then do not trend across the list)
   const int remap = (int64_t)A->sigma * 8 <= A->M;
+  if (LOGC == 6 && (A->params.flags & SPMV_FLAG_SPLIT4)) {  // g = one workgroup per chunk
+    if (A->perm)
+      launch(k_sell_kc4<T, true, KC>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+             (const T*)A->sval, (const T*)x, (T*)y, remap);
+    else
+      launch(k_sell_kc4<T, false, KC>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+             (const T*)A->sval, (const T*)x, (T*)y, remap);
+    return;
+  }
   if (A->perm)
     launch(k_sell_kc<T, LOGC, true, KC>, g, WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
            (const T*)A->sval, (const T*)x, (T*)y, remap);
@@ -894,7 +1022,8 @@ static spmv_status_t coo_pass(spmv_mat_s* A, int64_t e0, int64_t n, int64_t tb, 
 template <typename T>
 static spmv_status_t run_hyb_t(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
   if (A->M == 0) return SPMV_OK;
-  SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, !(A->params.flags & SPMV_FLAG_LINEAR), s));
+  SPMV_TRY(launch_ell<T>(A->M, A->K, A->ecol, A->eval, x, y, !(A->params.flags & SPMV_FLAG_LINEAR),
+                         (A->params.flags & SPMV_FLAG_SPLIT4) != 0, s));
   if (A->ncoo == 0) return SPMV_OK;
   if (A->coo_boff.empty()) return coo_pass<T>(A, 0, A->ncoo, 0, x, y, s);
   int64_t tb = 0;

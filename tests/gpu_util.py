@@ -55,17 +55,22 @@ FORMAT_CONFIGS = [
     ("csr5", {"csr5_sigma": 4, "bands": 8}),
     ("ell", {}),
     ("ell", {"flags": 4}),
+    ("ell", {"flags": 64}),
+    ("ell", {"flags": 64 | 4}),
     ("sell", {}),
     ("sell", {"flags": 8}),
     ("sell", {"sell_C": 64, "sell_sigma": 1}),
     ("sell", {"sell_C": 8, "sell_sigma": 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 16384}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1, "flags": 64}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "flags": 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "bands": 3}),
     ("sell", {"sell_C": 8, "sell_sigma": 1, "bands": 8}),
     ("sell", {"sell_C": 32, "sell_sigma": 64, "bands": 2, "flags": 8}),
     ("hyb", {}),
     ("hyb", {"hyb_K": 0}),
     ("hyb", {"hyb_K": 2}),
+    ("hyb", {"hyb_K": 2, "flags": 64}),
     ("hyb", {"bands": 3}),
     ("hyb", {"hyb_K": 1, "bands": 2}),
     ("hyb", {"hyb_K": 0, "bands": 4}),
