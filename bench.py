@@ -176,6 +176,15 @@ def _events(torch, stream, fn, steps, warmup, scrub, kernel_bound=True):
     return [a.elapsed_time(b) for a, b in pairs]
 
 
+def measured_traffic(args, label):
+    """HBM bytes per launch from the counter runs (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, profiles/traffic.json), or None."""
+    if not os.path.exists(args.traffic):
+        return None
+    tr = json.load(open(args.traffic)).get(f"{args.dtype}:{label}")
+    return tr.get("bytes_per_launch") if tr else None
+
+
 def bench_batch(args):
     """512 uneven CSR matrices (rows 10^3..2x10^5, mean row length 4..64,
     four generators, seed 8) in one persistent launch, against one launch
@@ -215,10 +224,12 @@ def bench_batch(args):
            "config": {"workload": f"512 uneven CSR matrices, {nnz} nnz, seed 8, "
                                   + ("warm cache" if args.warm else "cold cache")},
            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                        "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_csr_batched",
-                        "bytes_per_launch": int(bmin), "ms_per_launch": round(t, 5)},
+                        "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(args, "batch512"),
+                        "kernel": "k_csr_batched", "bytes_per_launch": int(bmin), "ms_per_launch": round(t, 5)},
            "one_launch_per_matrix": {"ms": round(t1, 5), "GBps": round(bmin / (t1 * 1e-3) / 1e9, 1)},
            "speedup_vs_per_matrix": round(t1 / t, 3)}
+    if args.copy_probe:
+        out["copy_probe_GBps"] = round(S.copy_probe(1 << 30, 20), 1)
     print(json.dumps(out), flush=True)
 
 
@@ -265,9 +276,11 @@ def bench_spmm(args):
            "config": {"workload": "27-pt stencil 100^3, X row-major N x k, k in {8, 16}, "
                                   + ("warm cache" if args.warm else "cold cache")},
            "roofline": {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                        "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_csr_spmm k=16",
-                        "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
+                        "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(args, "spmm/k16"),
+                        "kernel": "k_csr_spmm k=16", "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
            "per_k": per}
+    if args.copy_probe:
+        out["copy_probe_GBps"] = round(S.copy_probe(1 << 30, 20), 1)
     print(json.dumps(out), flush=True)
 
 

@@ -24,6 +24,7 @@ from __future__ import annotations
 import collections
 import csv
 import json
+import os
 import sys
 
 SCRUB = "k_scrub"
@@ -31,7 +32,8 @@ COPY = "k_copy"
 # kernels that spmv_run launches (conversion, feature and selection kernels
 # run outside the scrubbed launches and are not counted)
 RUN_KERNELS = ("k_band_sum", "k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix",
-               "k_c5_zero", "k_ell", "k_ell2", "k_ell_kc", "k_sell", "k_sell_kc", "k_sell_fix", "k_coo_tiles", "k_tile_fix", "k_csr_tiles")
+               "k_c5_zero", "k_ell", "k_ell2", "k_ell_kc", "k_ell_kc4", "k_sell", "k_sell_kc", "k_sell_kc4", "k_sell_fix",
+               "k_coo_tiles", "k_tile_fix", "k_csr_tiles", "k_csr_spmm", "k_csr_batched")
 
 
 def _short(name: str) -> str:
@@ -86,9 +88,23 @@ def _calibration(disp):
     return float(sum(copy) / len(copy)), float(1 << 30), COPY
 
 
-def traffic(fetch_csv: str, write_csv: str, bench_json: str, out_json: str):
+def _launches(bench):
+    """(label, algorithmic bytes, params, kernel that marks its launches) of
+    a benchmark line, in the order the benchmark runs them.  The SpMM line
+    runs k = 8 then k = 16 (each followed by k separate SpMVs, whose launches
+    hold no SpMM kernel); the batch line one batched launch per step."""
+    if "per_format" in bench:
+        return [(lab, v["bytes"], v["params"], None) for lab, v in bench["per_format"].items()]
+    if "per_k" in bench:
+        return [(f"spmm/{kk}", v["bytes"], None, "k_csr_spmm") for kk, v in bench["per_k"].items()]
+    return [("batch512", bench["roofline"]["bytes_per_launch"], None, "k_csr_batched")]
+
+
+def traffic(fetch_csv: str, write_csv: str, bench_json: str, out_json: str, merge: bool = True):
+    """HBM bytes per launch of the benchmark line in bench_json; with merge,
+    the entries are added to those already in out_json."""
     bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
-    labels = list(bench["per_format"].keys())
+    launches = _launches(bench)
     dt = bench["dtype"]
     F = _per_dispatch(fetch_csv, "FETCH_SIZE")
     Wr = _per_dispatch(write_csv, "WRITE_SIZE")
@@ -96,21 +112,29 @@ def traffic(fetch_csv: str, write_csv: str, bench_json: str, out_json: str):
     wm, wk, wsrc = _calibration(Wr)
     ff, wf = fk / fm, wk / wm
     sf, sw = _segments(F), _segments(Wr)
-    n = len(labels)
+    mark = launches[0][3]
+    if mark:  # keep the launches of the marking kernel only
+        sf = [g for g in sf if any(mark in k for k, _ in g)]
+        sw = [g for g in sw if any(mark in k for k, _ in g)]
+    n = len(launches)
     if len(sf) < n or len(sf) % n or len(sw) != len(sf):
         raise ValueError(f"{len(sf)} launches in the FETCH run, {len(sw)} in the WRITE run, {n} labels")
-    res = {"_calibration": {"fetch_factor": ff, "write_factor": wf, "kernel": fsrc,
-                            "fetch_raw_bytes": fm, "write_raw_bytes": wm, "known_bytes": fk}}
-    for i, lab in enumerate(labels):
-        fb = [sum(v for _, v in sf[j]) for j in range(i, len(sf), n)]
-        wb = [sum(v for _, v in sw[j]) for j in range(i, len(sw), n)]
+    res = json.load(open(out_json)) if merge and os.path.exists(out_json) else {}
+    res["_calibration"] = {"fetch_factor": ff, "write_factor": wf, "kernel": fsrc,
+                           "fetch_raw_bytes": fm, "write_raw_bytes": wm, "known_bytes": fk}
+    per = len(sf) // n
+    for i, (lab, alg, params, m) in enumerate(launches):
+        # per-format lines interleave their launches; marked lines run each
+        # label's launches back to back
+        idx = range(i * per, (i + 1) * per) if m else range(i, len(sf), n)
+        fb = [sum(v for _, v in sf[j]) for j in idx]
+        wb = [sum(v for _, v in sw[j]) for j in idx]
         fetch = ff * sum(fb) / len(fb)
         write = wf * sum(wb) / len(wb)
-        alg = bench["per_format"][lab]["bytes"]
         res[f"{dt}:{lab}"] = {"bytes_per_launch": int(round(fetch + write)), "fetch_bytes": int(round(fetch)),
                               "write_bytes": int(round(write)), "algorithmic_bytes": alg,
                               "ratio": round((fetch + write) / alg, 4),
-                              "kernels": [k for k, _ in sf[i]], "params": bench["per_format"][lab]["params"]}
+                              "kernels": sorted({k for j in idx for k, _ in sf[j]}), "params": params}
     json.dump(res, open(out_json, "w"), indent=1)
     return res
 
@@ -120,10 +144,12 @@ def main(argv):
         print(stats(argv[1]))
     elif argv[0] == "traffic":
         r = traffic(*argv[1:5])
+        labels = {f"{json.loads(open(argv[3]).read().strip().splitlines()[-1])['dtype']}:{lab}"
+                  for lab, _, _, _ in _launches(json.loads(open(argv[3]).read().strip().splitlines()[-1]))}
         for k, v in r.items():
             if k.startswith("_"):
                 print(k, v)
-            else:
+            elif k in labels:
                 print(f"{k:40s} measured {v['bytes_per_launch'] / 1e6:10.1f} MB  algorithmic "
                       f"{v['algorithmic_bytes'] / 1e6:10.1f} MB  ratio {v['ratio']:.3f}")
     elif argv[0] == "gather":
