@@ -139,8 +139,8 @@ spmv_status_t spmv_mat_from_coo(int64_t M, int64_t N, int64_t n, const int32_t* 
 /* Convert a CSR handle to fmt (Sec. II-B; Table I): a new handle.  p may be
  * NULL (defaults).  ELL/SELL/HYB above the byte cap -> TOO_LARGE.  The source
  * must be a CSR handle without column bands (INVALID_ARG otherwise); so must
- * the handles given to spmv_batch_create, spmv_autotune and spmv_features
- * (INVALID_ARG) and to spmv_spmm (UNSUPPORTED).
+ * the handles given to spmv_autotune and spmv_features (INVALID_ARG) and to
+ * spmv_spmm (UNSUPPORTED); spmv_batch_create also takes SELL handles.
  * Conversion runs on the device; it synchronises s (sizes come back). */
 spmv_status_t spmv_convert(spmv_mat_t csr, spmv_fmt_t fmt, const spmv_params_t* p, spmv_stream_t s,
                            spmv_mat_t* out);
@@ -183,11 +183,16 @@ spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64
 
 /* Not in the paper (it runs one matrix at a time; Sec. III-D splits one SpMV
  * into tasks -- rows, block rows, tiles -- and this extends the tasks over many
- * matrices).  Batched launch: n CSR handles of one dtype processed by ONE
- * kernel launch, one workgroup per item of a work list built at creation (row
- * blocks of every matrix, balanced by rows plus nonzeros); the hardware
- * dispatcher hands out the items, so the grid is not persistent.  create
- * builds the device work list; run takes host arrays of n device pointers. */
+ * matrices).  Batched launch: n handles of one dtype, each a CSR handle
+ * without column bands (its row blocks become items, whatever kernel its
+ * flags choose for spmv_run) or a SELL-C-sigma handle without column bands (groups of 256 / C
+ * chunks become items, one stored row per thread, slots summed 8 at a
+ * time), processed by ONE kernel launch, one workgroup per item of a work
+ * list built at creation; the hardware dispatcher hands out the items, so the
+ * grid is not persistent.  create builds the device work list (INVALID_ARG
+ * for other handles, mixed dtypes or a null handle; the handles must outlive
+ * the batch); run takes host arrays of n device pointers x[i] (N_i values)
+ * and y[i] (M_i values), and y[i] is overwritten. */
 spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* out);
 spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s);
 void spmv_batch_free(spmv_batch_t b);

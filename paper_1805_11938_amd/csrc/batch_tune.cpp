@@ -12,6 +12,7 @@ spmv_status_t launch_batched(int dt, int64_t nitems, const void* items, const vo
                              void* const* ys, int grid, hipStream_t s);
 size_t batch_item_size();
 spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s);
+int64_t batch_item_count(const spmv_mat_s* A);
 spmv_status_t time_run(spmv_mat_s* A, const void* x, void* y, int warmup, int min_reps, int max_reps, double rel_ci,
                        int64_t scrub_bytes, hipStream_t s, double out[5]);
 }  // namespace spmv
@@ -45,16 +46,17 @@ spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* ou
   if (!A || n <= 0 || !out) return fail(SPMV_ERR_INVALID_ARG, "batch arguments");
   *out = nullptr;
   for (int32_t i = 0; i < n; ++i) {
-    if (!A[i] || A[i]->fmt != SPMV_FMT_CSR || !A[i]->sub.empty())
-      return fail(SPMV_ERR_INVALID_ARG, "batch matrix %d is not a CSR handle without column bands", i);
+    if (!A[i] || (A[i]->fmt != SPMV_FMT_CSR && A[i]->fmt != SPMV_FMT_SELL) || !A[i]->sub.empty())
+      return fail(SPMV_ERR_INVALID_ARG, "batch matrix %d is not a CSR or SELL handle without column bands", i);
     if (A[i]->dt != A[0]->dt) return fail(SPMV_ERR_INVALID_ARG, "batch mixes dtypes");
+    if (A[i]->M >= INT32_MAX) return fail(SPMV_ERR_TOO_LARGE, "batch matrix %d has %lld rows", i, (long long)A[i]->M);
   }
   spmv_batch_s* b = new (std::nothrow) spmv_batch_s();
   if (!b) return fail(SPMV_ERR_OOM, "host allocation failed");
   b->n = n;
   b->dt = A[0]->dt;
   int64_t items = 0;
-  for (int32_t i = 0; i < n; ++i) items += A[i]->nblk;  // every row block of every matrix, in order
+  for (int32_t i = 0; i < n; ++i) items += batch_item_count(A[i]);  // every item of every matrix, in order
   b->nitems = items;
   const size_t is = batch_item_size();
   spmv_status_t st = dmalloc(&b->desc, is * (size_t)std::max<int64_t>(items, 1));
@@ -62,7 +64,7 @@ spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* ou
   int64_t at = 0;
   for (int32_t i = 0; i < n && st == SPMV_OK; ++i) {
     st = batch_items_fill(A[i], i, (char*)b->desc + is * at, nullptr);
-    at += A[i]->nblk;
+    at += batch_item_count(A[i]);
   }
   if (st == SPMV_OK && hipDeviceSynchronize() != hipSuccess) st = fail(SPMV_ERR_HIP, "batch item table build failed");
   if (st != SPMV_OK) {

@@ -881,12 +881,14 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
 // The item table, built once when the batch is created, holds each item's
 // matrix arrays, row range and nonzero range, so a workgroup issues its
 // column and value loads right after reading one record (no search over
-// the matrices, no dependent row-pointer loads).
+// the matrices, no dependent row-pointer loads).  A SELL-C-sigma matrix
+// contributes items of 256 / C chunks (one stored row per thread).
 struct BatchItem {
-  const int32_t* ptr;
+  const void* p0;  // CSR: ptr; SELL: cs (chunk slot offsets)
   const int32_t* col;
   const void* val;
-  int32_t m, r0, r1, k0, k1, pad;
+  const int32_t* perm;  // SELL with sigma > 1: stored row -> row (else null)
+  int32_t kind, m, r0, r1, k0, k1, logc, M;  // kind 0: CSR rows [r0, r1), entries [k0, k1); 1: SELL chunks [r0, r1)
 };
 
 __global__ void k_batch_items(int64_t nblk, const int32_t* __restrict__ blk_row, const int32_t* __restrict__ ptr,
@@ -894,17 +896,78 @@ __global__ void k_batch_items(int64_t nblk, const int32_t* __restrict__ blk_row,
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r0 = blk_row[b], r1 = blk_row[b + 1];
     BatchItem it;
-    it.ptr = ptr;
+    it.p0 = ptr;
     it.col = col;
     it.val = val;
+    it.perm = nullptr;
+    it.kind = 0;
     it.m = m;
     it.r0 = r0;
     it.r1 = r1;
     it.k0 = ptr[r0];
     it.k1 = ptr[r1];
-    it.pad = 0;
+    it.logc = 0;
+    it.M = 0;
     out[b] = it;
   }
+}
+
+__global__ void k_batch_sell_items(int64_t nitems, int64_t nchunks, int logc, int64_t M, const int64_t* cs,
+                                   const int32_t* perm, const int32_t* col, const void* val, int32_t m,
+                                   BatchItem* __restrict__ out) {
+  const int64_t per = BS >> logc;  // chunks per item
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nitems; b += (int64_t)gridDim.x * blockDim.x) {
+    BatchItem it;
+    it.p0 = cs;
+    it.col = col;
+    it.val = val;
+    it.perm = perm;
+    it.kind = 1;
+    it.m = m;
+    it.r0 = (int32_t)(b * per);
+    it.r1 = (int32_t)std::min<int64_t>(nchunks, (b + 1) * per);
+    it.k0 = 0;
+    it.k1 = 0;
+    it.logc = logc;
+    it.M = (int32_t)M;
+    out[b] = it;
+  }
+}
+
+// One SELL item: thread t takes stored row t & (C-1) of chunk r0 + (t >> log C)
+// and sums its slots 8 at a time (all loads of a group of 8 in flight;
+// padding slots hold column -1 and add nothing).
+template <typename T>
+__device__ __forceinline__ void sell_item(const BatchItem& it, const T* __restrict__ x, T* __restrict__ y) {
+  const int t = threadIdx.x;
+  const int64_t c = it.r0 + (t >> it.logc);
+  if (c >= it.r1) return;
+  const int p = t & ((1 << it.logc) - 1);
+  const int64_t* cs = (const int64_t*)it.p0;
+  const int64_t base = cs[c];
+  const int C = 1 << it.logc;
+  const int w = (int)((cs[c + 1] - base) >> it.logc);
+  const int32_t* cc = it.col + base + p;
+  const T* vv = (const T*)it.val + base + p;
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < w; k0 += 8) {
+    const int n = w - k0 < 8 ? w - k0 : 8;
+    int32_t cg[8];
+    T vg[8], xg[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cg[u] = ldnt(cc + (int64_t)(k0 + (u < n ? u : n - 1)) * C);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vg[u] = ldnt(vv + (int64_t)(k0 + (u < n ? u : n - 1)) * C);
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xg[u] = x[cg[u] >= 0 ? cg[u] : 0];
+    issue_fence();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sa[u & 3] += (u < n && cg[u] >= 0) ? (double)vg[u] * (double)xg[u] : 0.0;
+  }
+  const int64_t pos = c * C + p;
+  const int64_t r = it.perm ? (int64_t)it.perm[pos] : (pos < it.M ? pos : -1);
+  if (r >= 0) y[r] = (T)((sa[0] + sa[1]) + (sa[2] + sa[3]));
 }
 
 template <typename T>
@@ -920,11 +983,31 @@ __global__ __launch_bounds__(BS) void k_csr_batched(int64_t nitems, const BatchI
   const int64_t i = blockIdx.x;
   if (i >= nitems) return;
   const BatchItem it = items[i];
-  csr_rows_block<T>(it.r0, it.r1, it.k0, it.k1, it.ptr, it.col, (const T*)it.val, (const T*)xs[it.m],
-                    (T*)ys[it.m], prod, sptr);
+  if (it.kind == 1) {  // uniform over the workgroup
+    sell_item<T>(it, (const T*)xs[it.m], (T*)ys[it.m]);
+    return;
+  }
+  csr_rows_block<T>(it.r0, it.r1, it.k0, it.k1, (const int32_t*)it.p0, it.col, (const T*)it.val,
+                    (const T*)xs[it.m], (T*)ys[it.m], prod, sptr);
+}
+
+// Items of matrix A (index m of the batch): CSR row blocks or SELL chunk groups.
+int64_t batch_item_count(const spmv_mat_s* A) {
+  if (A->fmt == SPMV_FMT_SELL) return cdiv(A->nchunks, BS / A->C);
+  return A->nblk;
 }
 
 spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s) {
+  if (A->fmt == SPMV_FMT_SELL) {
+    const int64_t n = batch_item_count(A);
+    if (n <= 0) return SPMV_OK;
+    int logc = 0;
+    while ((1 << logc) < A->C) ++logc;
+    k_batch_sell_items<<<(unsigned)std::min<int64_t>(cdiv(n, BS), 1024), BS, 0, s>>>(
+        n, A->nchunks, logc, A->M, A->cs, A->perm, A->scol, A->sval, m, (BatchItem*)items);
+    SPMV_LAUNCH_CHECK();
+    return SPMV_OK;
+  }
   if (A->nblk <= 0) return SPMV_OK;
   k_batch_items<<<(unsigned)std::min<int64_t>(cdiv(A->nblk, BS), 1024), BS, 0, s>>>(
       A->nblk, A->blk_row, A->ptr, A->col, A->val, m, (BatchItem*)items);

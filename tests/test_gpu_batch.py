@@ -1,4 +1,4 @@
-"""GPU parity of the multi-RHS SpMM, the batched persistent launch and the
+"""GPU parity of the multi-RHS SpMM, the batched launch and the
 autotuner's choices, against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -100,6 +100,54 @@ def test_batched_matches_per_matrix_oracle(torch, dt):
         torch.cuda.synchronize()
         for y, (yref, den) in zip(ys, refs):
             assert rowwise_err(y.cpu().numpy().astype(np.float64), yref, den) <= TOL[dt]
+
+
+SELL_PARAMS = [dict(sell_C=64, sell_sigma=1), dict(sell_C=64, sell_sigma=1 << 30), dict(sell_C=32, sell_sigma=256),
+               dict(sell_C=8, sell_sigma=8), dict(sell_C=16, sell_sigma=1, flags=64), dict(sell_C=64, sell_sigma=4096)]
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+def test_mixed_csr_sell_batch_matches_per_matrix_oracle(torch, dt):
+    """One launch over CSR row blocks and SELL-C-sigma chunk groups of several
+    C and sigma (sorted and unsorted, chunks wider than 8 slots, rows of
+    thousands of entries, an empty matrix): every matrix meets the bar."""
+    specs = synth.batch_specs(20, seed=18, rows_lo=100, rows_hi=30_000)
+    mats = [synth.make(s) for s in specs]
+    mats.append(synth.zipf_rows(4000, 5000, 2.0, 16, 3000, 3, 4))
+    mats.append(synth.from_dense(np.zeros((33, 9))))
+    mats.append(synth.laplace2d(20))
+    handles, keep, xs, ys, refs = [], [], [], [], []
+    for i, A in enumerate(mats):
+        val = A.val.astype(np.float32) if dt == 1 else A.val
+        base = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt)
+        if i % 3 == 2:
+            handles.append(base)
+        else:
+            keep.append(base)
+            handles.append(base.convert("sell", **SELL_PARAMS[i % len(SELL_PARAMS)]))
+        x64 = synth.vector(A.N, 70 + i)
+        if dt == 1:
+            x64 = x64.astype(np.float32).astype(np.float64)
+        xs.append(device_vec(x64, dt))
+        ys.append(torch.full((A.M,), float("nan"), dtype=S.torch_dtype(dt), device="cuda"))
+        refs.append(reference(A, x64, dt))
+    assert {h.fmt for h in handles} == {"csr", "sell"}
+    B = S.Batch(handles)
+    for rep in range(2):
+        B.run(xs, ys)
+        torch.cuda.synchronize()
+        for j, (y, (yref, den)) in enumerate(zip(ys, refs)):
+            assert rowwise_err(y.cpu().numpy().astype(np.float64), yref, den) <= TOL[dt], (j, handles[j].fmt)
+
+
+def test_batch_rejects_other_formats(torch):
+    A = synth.laplace2d(8)
+    base = S.Matrix.from_host(A)
+    for fmt in ("csr5", "ell", "hyb"):
+        with pytest.raises(S.SpmvError):
+            S.Batch([base, base.convert(fmt)])
+    with pytest.raises(S.SpmvError):
+        S.Batch([base, base.convert("sell", bands=2)])
 
 
 @pytest.mark.parametrize("fmt", ["csr", "csr5", "ell", "sell", "hyb"])

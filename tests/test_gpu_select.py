@@ -144,3 +144,53 @@ def test_training_reduces_loss_like_the_oracle(torch):
     rel = np.abs(losses - np.array(ref)) / np.array(ref)
     # FP32 device training tracks the FP64 oracle; rounding differences grow slowly over the run
     assert np.max(rel[:5]) <= 1e-3 and np.max(rel) <= 5e-2, (losses[:5], ref[:5], rel)
+
+
+def test_training_epochs_match_the_oracle_from_the_same_start(torch):
+    """Each epoch of device training (spmv_mlp_train with epochs = 1, fresh
+    Adam moments per call) against the FP64 oracle's epoch started from the
+    parameters the device holds at that point, so rounding differences do not
+    compound over the run: the epoch's mean loss and the parameters after it
+    agree within FP32 accuracy."""
+    rng = np.random.default_rng(9)
+    n, epochs, batch = 96, 6, 32
+    X = rng.random((n, 12)).astype(np.float32)
+    y = (X[:, 0] * 5).astype(np.int32).clip(0, 4)
+    flat = np.concatenate([a.ravel() for a in synth.mlp_init(4)]).astype(np.float32)
+    dP = _dev(torch, flat.copy())
+    dX, dy = _dev(torch, X), _dev(torch, y)
+    shapes = [(12, 64), (64,), (64, 64), (64,), (64, 5), (5,)]
+
+    def unflat(v):
+        out, off = [], 0
+        for sh in shapes:
+            k = int(np.prod(sh))
+            out.append(np.asarray(v[off:off + k], np.float64).reshape(sh))
+            off += k
+        return out
+
+    for e in range(epochs):
+        start = dP.cpu().numpy().copy()
+        order = rng.permutation(n).astype(np.int32)
+        dord = _dev(torch, order)
+        loss = np.empty(1, np.float32)
+        S.check(S.lib().spmv_mlp_train(S.dptr(dP), S.dptr(dX), S.dptr(dy), n, S.dptr(dord), 1, batch, 1e-2,
+                                       S.stream(), S.hptr(loss)))
+        params = unflat(start)
+        mo = [np.zeros_like(a) for a in params]
+        vo = [np.zeros_like(a) for a in params]
+        ref = 0.0
+        for t, b0 in enumerate(range(0, n, batch), start=1):
+            idx = order[b0:b0 + batch]
+            lb, g = oracle.mlp_loss_and_grads(params, X[idx].astype(np.float64), y[idx])
+            ref += lb * len(idx) / n
+            params, mo, vo = oracle.adam_step(params, g, mo, vo, t, lr=1e-2)
+        assert abs(loss[0] - ref) <= 1e-5 * ref, (e, loss[0], ref)
+        got = dP.cpu().numpy().astype(np.float64)
+        want = np.concatenate([a.ravel() for a in params])
+        # an Adam step moves a parameter by at most about lr = 1e-2; FP32
+        # rounding changes it by far less, except where a gradient is so
+        # small that its FP32 and FP64 values differ in relative terms
+        d = np.abs(got - want)
+        assert np.max(d) <= 3e-2, (e, np.max(d))
+        assert np.mean(d <= 1e-5) >= 0.99, (e, np.mean(d <= 1e-5), np.sort(d)[-10:])
