@@ -86,8 +86,9 @@ typedef struct {
 #define SPMV_FLAG_CSR_WAVES 2u /* CSR: per-wave row units (+ long-row segments) instead of workgroup row blocks */
 #define SPMV_FLAG_LINEAR 4u    /* CSR row blocks, ELL and HYB's ELL part: workgroups take rows in launch order
                                   instead of each XCD taking a contiguous range of rows */
-#define SPMV_FLAG_SELL_SLICES 8u /* SELL: always the persistent column-slice kernel (default: chunks at most
-                                    32 wide use the one-pass narrow kernel) */
+#define SPMV_FLAG_SELL_SLICES 8u /* SELL: every chunk as column-slice items (default: chunks at most 32 wide
+                                    take one pass per stored row; wider chunks are cut into slices of 64
+                                    slots, run in the same launch, whose partial sums a fix-up adds) */
 #define SPMV_FLAG_CSR_BANDS 16u /* CSR: split the columns into 8 bands, one per XCD, so each XCD's L2 holds its
                                    eighth of x; per-band partial sums are added by a second pass */
 #define SPMV_FLAG_CSR_TILES 32u /* CSR: one wave per tile of 1,024 consecutive nonzeros (segmented scan in

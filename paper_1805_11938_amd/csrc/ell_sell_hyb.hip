@@ -483,61 +483,9 @@ __global__ void k_sell_to_csr(int64_t M, int64_t Mpad, int C, const int32_t* per
 // A work item is a slice of at most SELL_KT columns of one chunk, run by C
 // lanes (one per stored row).  Chunks of one slice write y directly; wider
 // chunks write per-slice partial sums that k_sell_fix adds in slice order.
+// The items run in k_sell_mixed, beside the narrow chunks.
 constexpr int SELL_KT = 64;
 constexpr int SELL_KC_MAX = 32;  // widest chunk the one-pass narrow kernel takes
-
-template <typename T, int LOGC, bool PERM>
-__global__ __launch_bounds__(BS) void k_sell(int64_t M, int64_t nitems, const int2* __restrict__ items,
-                                             const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
-                                             const int32_t* __restrict__ scol, const T* __restrict__ sval,
-                                             const T* __restrict__ x, T* __restrict__ y, double* __restrict__ part) {
-  constexpr int C = 1 << LOGC;
-  for (int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x; (gid >> LOGC) < nitems;
-       gid += (int64_t)gridDim.x * BS) {
-  const int64_t it = gid >> LOGC;
-  const int p = (int)(gid & (C - 1));
-  const int2 im = items[it];
-  const int64_t c = im.x, k0 = im.y;
-  const int64_t base = cs[c];
-  const int64_t w = (cs[c + 1] - base) >> LOGC;
-  const int64_t k1 = w < k0 + SELL_KT ? w : k0 + SELL_KT;
-  const int32_t* cc = scol + base + p;
-  const T* vv = sval + base + p;
-  double sa[4] = {0.0, 0.0, 0.0, 0.0};
-  {
-    int64_t k = k0;
-    for (; k + 7 < k1; k += 8) {
-      int32_t c8[8];
-      T v8[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) c8[u] = ldnt(cc + (k + u) * C);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v8[u] = ldnt(vv + (k + u) * C);
-      issue_fence();
-      T x8[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x8[u] = ld32(x, (uint32_t)(c8[u] >= 0 ? c8[u] : 0));
-      issue_fence();
-#pragma unroll
-      for (int u = 0; u < 8; ++u) sa[u & 3] += c8[u] >= 0 ? (double)v8[u] * (double)x8[u] : 0.0;
-    }
-    for (; k < k1; ++k) {
-      const int32_t c0 = ldnt(cc + k * C);
-      const T v0 = ldnt(vv + k * C);
-      const T x0 = x[c0 >= 0 ? c0 : 0];
-      sa[0] += c0 >= 0 ? (double)v0 * (double)x0 : 0.0;
-    }
-  }
-  const double s = (sa[0] + sa[1]) + (sa[2] + sa[3]);
-  if (w <= SELL_KT) {
-    const int64_t pos = c * C + p;
-    const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-    if (r >= 0) y[r] = (T)s;
-  } else {
-    part[it * C + p] = s;
-  }
-  }
-}
 
 // The slots of one stored row, KW places (KW >= w): every slot's column and
 // value load in flight at once, then every gather, then the sum.  Places
@@ -635,6 +583,77 @@ __global__ __launch_bounds__(4 * WAVE) void k_sell_kc4(int64_t M, int64_t c0, in
   }
 }
 
+// SELL with wide chunks, one launch: the first nwg_wide workgroups (one wave
+// each) take the column slices of the chunks before kc_first (64 slots of one
+// chunk per item, C lanes per item), the rest the narrow chunks [c0, nchunks)
+// as k_sell_kc does.  The slices start first and keep up to 32 slots of a
+// stored row in flight, so their long dependent chains overlap the narrow
+// chunks instead of following them.  nwg_wide is a multiple of 8, so the
+// narrow part's XCD-aware order holds.
+template <typename T, int LOGC, bool PERM, int KC>
+__global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, const int2* __restrict__ items,
+                                                     int64_t nwg_wide, int64_t c0, int64_t nchunks,
+                                                     const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ scol, const T* __restrict__ sval,
+                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                     double* __restrict__ part, int remap) {
+  constexpr int C = 1 << LOGC;
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  if ((int64_t)blockIdx.x < nwg_wide) {
+    const int64_t gid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+    const int64_t it = gid >> LOGC;
+    if (it >= nitems) return;
+    const int p = (int)(gid & (C - 1));
+    const int2 im = items[it];
+    const int64_t c = im.x, k0 = im.y;
+    const int64_t base = cs[c];
+    const int64_t w = (cs[c + 1] - base) >> LOGC;
+    // 0..64 slots of this slice (0: a chunk of empty rows, e.g. a column band
+    // that misses them, has one item and nothing to load)
+    const int n = (int)((w < k0 + SELL_KT ? w : k0 + SELL_KT) - k0);
+    const int32_t* cc = scol + base + k0 * C + p;
+    const T* vv = sval + base + k0 * C + p;
+    if (n <= 0) {
+    } else if (n > 32) {
+      sell_slots<T, LOGC, 32>(cc, vv, x, 32, sa);
+      sell_slots<T, LOGC, 32>(cc + 32 * C, vv + 32 * C, x, n - 32, sa);
+    } else if (n > 16) {
+      sell_slots<T, LOGC, 32>(cc, vv, x, n, sa);
+    } else if (n > 8) {
+      sell_slots<T, LOGC, 16>(cc, vv, x, n, sa);
+    } else {
+      sell_slots<T, LOGC, 8>(cc, vv, x, n, sa);
+    }
+    const double s = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+    if (w <= SELL_KT) {
+      const int64_t pos = c * C + p;
+      const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+      if (r >= 0) y[r] = (T)s;
+    } else {
+      part[it * C + p] = s;
+    }
+    return;
+  }
+  const uint32_t nb = gridDim.x - (uint32_t)nwg_wide, b = blockIdx.x - (uint32_t)nwg_wide;
+  const int64_t gid = (int64_t)(remap ? xcd_block(b, nb) : b) * WAVE + threadIdx.x;
+  const int64_t c = c0 + (LOGC == 6 ? (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(gid >> 6)) : gid >> LOGC);
+  if (c >= nchunks) return;
+  const int p = (int)(gid & (C - 1));
+  const int64_t base = cs[c];
+  const int w = (int)((cs[c + 1] - base) >> LOGC);
+  if (w > 0) {
+    const int32_t* cc = scol + base + p;
+    const T* vv = sval + base + p;
+    if (KC > 16 && w > 16) sell_slots<T, LOGC, KC>(cc, vv, x, w, sa);
+    else if (KC > 8 && w > 8) sell_slots<T, LOGC, (KC < 16 ? KC : 16)>(cc, vv, x, w, sa);
+    else if (KC > 4 && w > 4) sell_slots<T, LOGC, (KC < 8 ? KC : 8)>(cc, vv, x, w, sa);
+    else sell_slots<T, LOGC, (KC < 4 ? KC : 4)>(cc, vv, x, w, sa);
+  }
+  const int64_t pos = c * C + p;
+  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+  if (r >= 0) y[r] = (T)((sa[0] + sa[1]) + (sa[2] + sa[3]));
+}
+
 // one thread per (wide chunk, stored row): y = sum of the slices' partials in order
 template <typename T, bool PERM>
 __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restrict__ wide,
@@ -664,7 +683,25 @@ __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restri
 }
 
 template <typename T, int LOGC, int KC>
+static void launch_sell_mixed(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  const int64_t nwide = cdiv(cdiv(A->nitems << LOGC, WAVE), 8) * 8;
+  const int64_t nnarrow = cdiv((A->nchunks - A->kc_first) << LOGC, WAVE);
+  const int remap = (int64_t)A->sigma * 8 <= A->M;
+  const unsigned g = (unsigned)(nwide + nnarrow);
+  if (A->perm)
+    launch(k_sell_mixed<T, LOGC, true, KC>, g, WAVE, s, A->M, A->nitems, A->items, nwide, A->kc_first, A->nchunks,
+           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap);
+  else
+    launch(k_sell_mixed<T, LOGC, false, KC>, g, WAVE, s, A->M, A->nitems, A->items, nwide, A->kc_first, A->nchunks,
+           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap);
+}
+
+template <typename T, int LOGC, int KC>
 static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
+  if (A->kc_first > 0) {  // wide chunks too: one launch for both (the slices' fix-up follows)
+    launch_sell_mixed<T, LOGC, KC>(A, x, y, s);
+    return;
+  }
   const unsigned g = (unsigned)cdiv((A->nchunks - A->kc_first) << LOGC, WAVE);
   // contiguous ranges per XCD only while a sort window is small next to an
   // XCD's share of the rows (chunk widths then do not trend across the list)
@@ -691,7 +728,7 @@ static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s)
 // rows) through the column-slice items.  Both write disjoint rows of y.
 template <typename T, int LOGC>
 static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  if (A->kc_first < A->nchunks) {
+  if (A->kc_first < A->nchunks || A->kc_first > 0) {
     if (LOGC == 6) {  // one chunk per wave: instantiated for the exact widest chunk
       switch (A->kc_w) {
       case 1: launch_sell_kc<T, 6, 1>(A, x, y, s); break;
@@ -735,13 +772,6 @@ static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) 
     }
   }
   if (A->kc_first == 0) return;
-  const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nitems << LOGC, BS), resident_blocks(8));
-  if (A->perm)
-    launch(k_sell<T, LOGC, true>, g, BS, s, A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
-                                           (const T*)x, (T*)y, A->part);
-  else
-    launch(k_sell<T, LOGC, false>, g, BS, s, A->M, A->nitems, A->items, A->cs, A->perm, A->scol, (const T*)A->sval,
-                                            (const T*)x, (T*)y, A->part);
   if (A->nwide > 0) {
     const unsigned gf = (unsigned)cdiv(A->nwide << LOGC, BS);
     if (A->perm)
