@@ -263,6 +263,8 @@ def selector_spec(i: int, seed0: int = 100, kinds=GENERATORS, nnz_lo=1e5, nnz_hi
     """Parameters of matrix i of the selector training set.  Generator kinds
     rotate, so each kind gets an equal share.  Parameters are resampled until
     the expected nnz lies in [nnz_lo, nnz_hi]."""
+    if i >= N_BASE:
+        return selector_spec_large(i, seed0)
     kind = kinds[i % len(kinds)]
     rng = np.random.default_rng(seed0 + i)
     for _ in range(1000):
@@ -301,6 +303,48 @@ def selector_spec(i: int, seed0: int = 100, kinds=GENERATORS, nnz_lo=1e5, nnz_hi
     raise RuntimeError(f"could not sample spec {i}")
 
 
+LARGE_KINDS = ("stencil27", "banded", "uniform", "zipf", "rmat")
+N_BASE = 3000  # matrices 0..2999: the base set; from 3000 on: the large set
+
+
+def selector_spec_large(i: int, seed0: int = 100) -> dict:
+    """Matrix i >= N_BASE of the selector training set: the large shapes
+    (2x10^7..3x10^8 nonzeros, 10^6..1.7x10^7 rows) of the benchmark matrices --
+    3-D 27-point stencils on n^3 grids besides banded, uniform, Zipf and R-MAT."""
+    j = i - N_BASE
+    kind = LARGE_KINDS[j % len(LARGE_KINDS)]
+    rng = np.random.default_rng(seed0 + i)
+    for _ in range(1000):
+        if kind == "stencil27":
+            n = int(rng.integers(100, 221))
+            return dict(index=i, kind=kind, M=n ** 3, seed=seed0 + i, params=dict(n=n))
+        M = int(_loguniform(rng, 1e6, 1.7e7))
+        if kind == "banded":
+            hw = int(round(_loguniform(rng, 4, 64)))
+            fill = float(rng.uniform(0.2, 1.0))
+            exp_nnz = M * (1 + 2 * hw * fill)
+            p = dict(halfwidth=hw, fill=fill)
+        elif kind == "uniform":
+            mean = float(rng.uniform(4, 32))
+            exp_nnz = M * mean
+            p = dict(mean=mean)
+        elif kind == "zipf":
+            alpha = float(rng.uniform(1.5, 3.0))
+            mean = float(rng.uniform(8, 32))
+            lmax = int(round(_loguniform(rng, 1e3, 1e4)))
+            exp_nnz = M * mean
+            p = dict(alpha=alpha, mean=mean, lmax=lmax)
+        else:  # rmat
+            scale = int(rng.integers(20, 25))
+            M = 1 << scale
+            ef = float(rng.uniform(4, 16))
+            exp_nnz = M * ef * 0.9
+            p = dict(scale=scale, edge_factor=ef)
+        if 2e7 <= exp_nnz <= 3e8:
+            return dict(index=i, kind=kind, M=M, seed=seed0 + i, params=p)
+    raise RuntimeError(f"could not sample spec {i}")
+
+
 def selector_specs(n: int = 3000, seed0: int = 100, **kw) -> list[dict]:
     return [selector_spec(i, seed0, **kw) for i in range(n)]
 
@@ -321,6 +365,8 @@ def make(spec: dict):
         return zipf_rows(M, M, p["alpha"], p["mean"], p["lmax"], s, vs)
     if k == "rmat":
         return rmat_coo(p["scale"], int(round(p["edge_factor"] * M)), s, vs)
+    if k == "stencil27":
+        return stencil27(p["n"], vs)
     raise ValueError(k)
 
 
