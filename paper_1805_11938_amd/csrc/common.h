@@ -422,24 +422,6 @@ __device__ __forceinline__ void seg_scan64(double& v, int32_t& f) {
   seg_step<DPP_ROW_BCAST15, 0xa>(v, f);
   seg_step<DPP_ROW_BCAST31, 0xc>(v, f);
 }
-// inclusive prefix sum over the 64 lanes
-__device__ __forceinline__ int32_t add_scan64(int32_t v) {
-  v += dpp_i<DPP_ROW_SR1, 0xf>(v, 0);
-  v += dpp_i<DPP_ROW_SR2, 0xf>(v, 0);
-  v += dpp_i<DPP_ROW_SR4, 0xf>(v, 0);
-  v += dpp_i<DPP_ROW_SR8, 0xf>(v, 0);
-  v += dpp_i<DPP_ROW_BCAST15, 0xa>(v, 0);
-  v += dpp_i<DPP_ROW_BCAST31, 0xc>(v, 0);
-  return v;
-}
-// lane l receives lane src's value (src taken mod 64)
-__device__ __forceinline__ int32_t perm_i(int32_t v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
-__device__ __forceinline__ double perm_d(double v, int src) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int32_t)(uint32_t)b);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int32_t)(uint32_t)(b >> 32));
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 // inclusive running maximum over the 64 lanes (values >= -1)
 __device__ __forceinline__ int32_t max_scan64(int32_t v) {
   constexpr int32_t LOW = -2147483647 - 1;

@@ -366,16 +366,15 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
   const int64_t row0 = W64 ? (int64_t)__builtin_amdgcn_readfirstlane(a.tile_ptr[t]) : (int64_t)a.tile_ptr[t];
   const bool cont = a.ptr[row0] < base;
   const int64_t nzb = EMPTY ? a.nzbase[t] : 0;
-  // y_off: flags in earlier lanes of the tile (a DPP prefix sum for 64-lane tiles)
+  // y_off: flags in earlier lanes of the tile.  (The lane scans stay on
+  // cross-lane shuffles: DPP versions of both scans left the stencil's time
+  // unchanged and, by raising occupancy, made the sigma = 32 tiles over two
+  // column bands of a Zipf matrix slower, 174 -> 189 us.)
   const int pc = __popc(F);
   int inc = pc;
-  if (W64) {
-    inc = add_scan64(pc);
-  } else {
-    for (int d = 1; d < omega; d <<= 1) {
-      const int u = __shfl_up(inc, d, omega);
-      if (l >= d) inc += u;
-    }
+  for (int d = 1; d < omega; d <<= 1) {
+    const int u = __shfl_up(inc, d, omega);
+    if (l >= d) inc += u;
   }
   const int yoff = inc - pc;
   double acc = 0.0, head = 0.0;
@@ -422,31 +421,19 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
   }
   if (!seen) head = acc;
   // reverse segmented scan over the tile's lanes: R_l = head_l + (lane l
-  // flag-free ? R_{l+1} : 0), so R_{l+1} completes lane l's open segment.
-  // 64-lane tiles: in mirrored lane order (l' = 63 - l) this is the forward
-  // segmented scan R'_l' = head' + (flag' ? 0 : R'_{l'-1}) with DPP steps;
-  // lane l then needs R_{l+1} = R'_{62-l}.
-  double S;
-  if (W64) {
-    double Rv = perm_d(head, WAVE - 1 - l);
-    int32_t Rs = perm_i(seen ? 1 : 0, WAVE - 1 - l);
-    seg_scan64(Rv, Rs);
-    S = perm_d(Rv, WAVE - 2 - l);
-    if (l == WAVE - 1) S = 0.0;
-  } else {
-    double Rv = head;
-    int Rs = seen ? 1 : 0;
-    for (int d = 1; d < omega; d <<= 1) {
-      const double ov = __shfl_down(Rv, d, omega);
-      const int os = __shfl_down(Rs, d, omega);
-      if (l + d < omega && !Rs) {
-        Rv += ov;
-        Rs = os;
-      }
+  // flag-free ? R_{l+1} : 0), so R_{l+1} completes lane l's open segment
+  double Rv = head;
+  int Rs = seen ? 1 : 0;
+  for (int d = 1; d < omega; d <<= 1) {
+    const double ov = __shfl_down(Rv, d, omega);
+    const int os = __shfl_down(Rs, d, omega);
+    if (l + d < omega && !Rs) {
+      Rv += ov;
+      Rs = os;
     }
-    S = __shfl_down(Rv, 1, omega);
-    if (l == omega - 1) S = 0.0;
   }
+  double S = __shfl_down(Rv, 1, omega);
+  if (l == omega - 1) S = 0.0;
   if (seen) c5_write<T, EMPTY>(a, t, row0, nzb, cont, yoff + lf - 1, acc + S, y);
 }
 
