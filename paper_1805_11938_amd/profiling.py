@@ -3,7 +3,9 @@
 Two uses:
 
 * ``stats``: per-kernel call counts and average durations from a
-  ``--kernel-trace --stats`` run (``*_kernel_stats.csv``), as text.
+  ``--kernel-trace --stats`` run (``*_kernel_stats.csv``), as text;
+  ``launches``: the span of each benchmark launch in the same run's trace
+  (``*_kernel_trace.csv``).
 * ``traffic``: HBM bytes per benchmark launch from two counter runs
   (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``; both counters are KiB per
   dispatch).  The benchmark scrubs the caches before every launch, so the
@@ -16,6 +18,7 @@ Two uses:
   1, 4, 8 and 16 MB and 16.7 million gathers, FP64 and FP32 (needs the GPU).
 
     python -m paper_1805_11938_amd.profiling stats DIR/..._kernel_stats.csv
+    python -m paper_1805_11938_amd.profiling launches DIR/..._kernel_trace.csv BENCH.json
     python -m paper_1805_11938_amd.profiling traffic FETCH.csv WRITE.csv BENCH.json OUT.json
     python -m paper_1805_11938_amd.profiling gather
 """
@@ -24,6 +27,7 @@ from __future__ import annotations
 import collections
 import csv
 import json
+import math
 import os
 import sys
 
@@ -139,9 +143,52 @@ def traffic(fetch_csv: str, write_csv: str, bench_json: str, out_json: str, merg
     return res
 
 
+def launches(trace_csv: str, bench_json: str) -> str:
+    """Per benchmark launch: the span from the first run kernel's start to
+    the last one's end, from a --kernel-trace run of the benchmark (its
+    launches follow the scrub kernels in the benchmark's order), next to the
+    same run's kernel-bound event times and algorithmic bytes."""
+    bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    labs = _launches(bench)
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
+    segs, cur = [], None
+    for r in rows:
+        k = _short(r["Kernel_Name"])
+        if SCRUB in k:
+            if cur:
+                segs.append(cur)
+            cur = []
+        elif cur is not None and k.split("<")[0].split("::")[-1] in RUN_KERNELS:
+            cur.append((k, int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    if cur:
+        segs.append(cur)
+    mark = labs[0][3]
+    if mark:
+        segs = [g for g in segs if any(mark in k for k, _, _ in g)]
+    n = len(labs)
+    if len(segs) < n or len(segs) % n:
+        raise ValueError(f"{len(segs)} launches in the trace for {n} labels")
+    per = len(segs) // n
+    out = ["| launch | kernels | rocprofv3 µs | benchmark events µs | algorithmic MB | GB/s (rocprof) |",
+           "|---|---|---|---|---|---|"]
+    for i, (lab, alg, _, m) in enumerate(labs):
+        idx = range(i * per, (i + 1) * per) if m else range(i, len(segs), n)
+        spans = [(segs[j][-1][2] - segs[j][0][1]) / 1e3 for j in idx]
+        us = sum(spans) / len(spans)
+        ks = []
+        for k, _, _ in segs[idx[0]]:
+            if k not in ks:
+                ks.append(k)
+        ev = bench["per_format"][lab]["ms"] * 1e3 if "per_format" in bench else math.nan
+        out.append(f"| {lab} | {', '.join(ks)} | {us:.2f} | {ev:.2f} | {alg / 1e6:.1f} | {alg / us / 1e3:.0f} |")
+    return "\n".join(out)
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats(argv[1]))
+    elif argv[0] == "launches":
+        print(launches(argv[1], argv[2]))
     elif argv[0] == "traffic":
         r = traffic(*argv[1:5])
         labels = {f"{json.loads(open(argv[3]).read().strip().splitlines()[-1])['dtype']}:{lab}"
