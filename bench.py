@@ -190,21 +190,30 @@ BATCH_SELL = dict(sell_C=64, sell_sigma=4096)
 
 def batch_formats(args, mats, dt):
     """The handle each matrix enters the batch as.  --batch-format csr or sell
-    takes one format for all; auto takes SELL-C-sigma chunk groups for
-    matrices with regular rows (coefficient of variation of the row lengths
-    at most 0.5 and no row over 256 entries, from the device features: one
-    lane per row then has an even share and padding stays small) and CSR
-    row blocks for the rest, whose long rows a whole workgroup shares.
+    takes one format for all (tiles: CSR wave tiles); auto takes SELL-C-sigma
+    chunk groups for matrices with regular rows (coefficient of variation of
+    the row lengths at most 0.5 and no row over 256 entries, from the device
+    features: one lane per row then has an even share and padding stays
+    small) and CSR wave tiles for the rest, whose long rows spread over
+    tiles of equal size.
     Returns (handles, count per format)."""
     out = []
     for m in mats:
         if args.batch_format == "auto":
             f = m.features()  # n_rows, n_cols, nnz, nnz_frac, min, max, avg, std, variation, ...
-            fmt = "sell" if f[8] <= 0.5 and f[5] <= 256 else "csr"
+            fmt = "sell" if f[8] <= 0.5 and f[5] <= 256 else "tiles"
         else:
             fmt = args.batch_format
-        out.append(m.convert("sell", **BATCH_SELL) if fmt == "sell" else m)
-    return out, {f: sum(1 for h in out if h.fmt == f) for f in ("csr", "sell")}
+        if fmt == "sell":
+            out.append(m.convert("sell", **BATCH_SELL))
+        elif fmt == "tiles":
+            out.append(m.convert("csr", flags=32))
+        else:
+            out.append(m)
+    kinds = {"csr": sum(1 for h in out if h.fmt == "csr" and not h.params["flags"] & 32),
+             "csr_tiles": sum(1 for h in out if h.fmt == "csr" and h.params["flags"] & 32),
+             "sell": sum(1 for h in out if h.fmt == "sell")}
+    return out, kinds
 
 
 def bench_batch(args):
@@ -319,9 +328,9 @@ def main():
     ap.add_argument("--only", default="", help="comma-separated matrix/format labels to run (default: all)")
     ap.add_argument("--warm", action="store_true", help="skip the cache scrub between launches (labelled warm)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain 1 GiB device copy")
-    ap.add_argument("--batch-format", default="auto", choices=["auto", "csr", "sell"],
+    ap.add_argument("--batch-format", default="auto", choices=["auto", "csr", "sell", "tiles"],
                     help="batch512: the format each matrix enters the batch as (auto: SELL-C-sigma for "
-                         "regular rows, CSR otherwise)")
+                         "regular rows, CSR wave tiles otherwise)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE), if present")
     args = ap.parse_args()

@@ -185,12 +185,15 @@ spmv_status_t spmv_spmm(spmv_mat_t A, const void* X, int64_t ldx, void* Y, int64
 /* Not in the paper (it runs one matrix at a time; Sec. III-D splits one SpMV
  * into tasks -- rows, block rows, tiles -- and this extends the tasks over many
  * matrices).  Batched launch: n handles of one dtype, each a CSR handle
- * without column bands (its row blocks become items, whatever kernel its
- * flags choose for spmv_run) or a SELL-C-sigma handle without column bands (groups of 256 / C
- * chunks become items, one stored row per thread, slots summed 8 at a
- * time), processed by ONE kernel launch, one workgroup per item of a work
- * list built at creation; the hardware dispatcher hands out the items, so the
- * grid is not persistent.  create builds the device work list (INVALID_ARG
+ * without column bands (its row blocks become items; built with
+ * SPMV_FLAG_CSR_TILES, its wave tiles, four per item), or a SELL-C-sigma
+ * handle without column bands (groups of 256 / C chunks become items, one
+ * stored row per thread, slots summed 8 at a time), processed by ONE kernel
+ * launch, one workgroup per item of a work list built at creation; the
+ * hardware dispatcher hands out the items, so the grid is not persistent.
+ * When wave-tile handles are present, a second, small kernel adds the partial
+ * sums of their rows that cross tiles, in tile order (each such handle's tile
+ * scratch is shared with its spmv_run: runs of one handle must not overlap).  create builds the device work list (INVALID_ARG
  * for other handles, mixed dtypes or a null handle; the handles must outlive
  * the batch); run takes host arrays of n device pointers x[i] (N_i values)
  * and y[i] (M_i values), and y[i] is overwritten. */

@@ -13,6 +13,10 @@ spmv_status_t launch_batched(int dt, int64_t nitems, const void* items, const vo
 size_t batch_item_size();
 spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s);
 int64_t batch_item_count(const spmv_mat_s* A);
+size_t batch_tiles_size();
+spmv_status_t batch_tile_items(const spmv_mat_s* A, int32_t m, void* host_rec, const void* dev_rec, void* items,
+                               hipStream_t s);
+spmv_status_t launch_batch_tile_fix(int dt, int32_t ntm, const void* recs, void* const* ys, hipStream_t s);
 spmv_status_t time_run(spmv_mat_s* A, const void* x, void* y, int warmup, int min_reps, int max_reps, double rel_ci,
                        int64_t scrub_bytes, hipStream_t s, double out[5]);
 }  // namespace spmv
@@ -25,6 +29,8 @@ struct spmv_batch_s {
   int64_t nitems = 0;
   void* desc = nullptr;   // device: one record per work item (matrix, row and nonzero range)
   void** xy = nullptr;    // device: n x pointers then n y pointers
+  int32_t ntm = 0;        // matrices run as CSR wave tiles
+  void* tiles = nullptr;  // device: their records (arrays, tile tables, batch index), for the fix-up pass
   std::vector<const void*> last;  // host copy of the pointers last uploaded
 };
 
@@ -61,15 +67,30 @@ spmv_status_t spmv_batch_create(const spmv_mat_t* A, int32_t n, spmv_batch_t* ou
   const size_t is = batch_item_size();
   spmv_status_t st = dmalloc(&b->desc, is * (size_t)std::max<int64_t>(items, 1));
   if (st == SPMV_OK) st = dmalloc((void**)&b->xy, sizeof(void*) * 2 * n);
+  for (int32_t i = 0; i < n; ++i)
+    if (A[i]->fmt == SPMV_FMT_CSR && A[i]->ntiles_csr > 0) ++b->ntm;
+  const size_t ts = batch_tiles_size();
+  std::vector<char> hrec(ts * (size_t)std::max<int32_t>(b->ntm, 1));
+  if (st == SPMV_OK && b->ntm > 0) st = dmalloc(&b->tiles, ts * (size_t)b->ntm);
   int64_t at = 0;
+  int32_t tm = 0;
   for (int32_t i = 0; i < n && st == SPMV_OK; ++i) {
-    st = batch_items_fill(A[i], i, (char*)b->desc + is * at, nullptr);
+    if (A[i]->fmt == SPMV_FMT_CSR && A[i]->ntiles_csr > 0) {
+      st = batch_tile_items(A[i], i, hrec.data() + ts * tm, (char*)b->tiles + ts * tm, (char*)b->desc + is * at,
+                            nullptr);
+      ++tm;
+    } else {
+      st = batch_items_fill(A[i], i, (char*)b->desc + is * at, nullptr);
+    }
     at += batch_item_count(A[i]);
   }
+  if (st == SPMV_OK && b->ntm > 0 && hipMemcpy(b->tiles, hrec.data(), ts * b->ntm, hipMemcpyHostToDevice) != hipSuccess)
+    st = fail(SPMV_ERR_HIP, "batch tile records upload failed");
   if (st == SPMV_OK && hipDeviceSynchronize() != hipSuccess) st = fail(SPMV_ERR_HIP, "batch item table build failed");
   if (st != SPMV_OK) {
     dfree(b->desc);
     dfree(b->xy);
+    dfree(b->tiles);
     delete b;
     return st;
   }
@@ -92,8 +113,9 @@ spmv_status_t spmv_batch_run(spmv_batch_t b, const void* const* x, void* const* 
     b->last = ptrs;
   }
   if (b->nitems > INT32_MAX) return fail(SPMV_ERR_TOO_LARGE, "batch of %lld row blocks", (long long)b->nitems);
-  const int grid = (int)std::max<int64_t>(b->nitems, 1);  // one workgroup per row block
-  return launch_batched(b->dt, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st);
+  const int grid = (int)std::max<int64_t>(b->nitems, 1);  // one workgroup per item
+  SPMV_TRY(launch_batched(b->dt, b->nitems, b->desc, (const void* const*)b->xy, b->xy + b->n, grid, st));
+  return launch_batch_tile_fix(b->dt, b->ntm, b->tiles, b->xy + b->n, st);
 }
 
 spmv_status_t spmv_batch_run_timed(spmv_batch_t b, const void* const* x, void* const* y, spmv_stream_t s,
@@ -107,6 +129,7 @@ void spmv_batch_free(spmv_batch_t b) {
   if (!b) return;
   dfree(b->desc);
   dfree(b->xy);
+  dfree(b->tiles);
   delete b;
 }
 

@@ -15,6 +15,8 @@
 //
 // Alternative kernel ("vector-V"): V lanes per row over a flat row grid,
 // the rows-per-wavefront knob of the autotuner (64/V rows per wave).
+#include <cstring>
+
 #include "common.h"
 
 namespace spmv {
@@ -601,21 +603,18 @@ __global__ void k_csr_tile_rows(int64_t M, int64_t nnz, int64_t ntiles, const in
   }
 }
 
+// One tile t of a CSR (entries [t*TILE_E, ...) of col / val) by one wave:
+// rows marked in the wave's LDS table rw, then the segmented reduction.
 template <typename T>
-__global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
-                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                  const int32_t* __restrict__ tstart, const int32_t* __restrict__ tcont,
-                                                  const T* __restrict__ x, T* __restrict__ y,
-                                                  double* __restrict__ head_part, double* __restrict__ tail_part,
-                                                  int32_t* __restrict__ tail_row, int32_t* __restrict__ tinfo) {
-  __shared__ int32_t rid[BS / WAVE][TILE_E];
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int64_t t = (int64_t)blockIdx.x * (BS / WAVE) + w;
-  if (t >= ntiles) return;
+__device__ __forceinline__ void csr_tile(int64_t t, int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
+                                         const int32_t* __restrict__ col, const T* __restrict__ val,
+                                         const int32_t* __restrict__ tstart, const int32_t* __restrict__ tcont,
+                                         const T* __restrict__ x, T* __restrict__ y, double* __restrict__ head_part,
+                                         double* __restrict__ tail_part, int32_t* __restrict__ tail_row,
+                                         int32_t* __restrict__ tinfo, int32_t* rw) {
   const int l = __lane_id();
   const int64_t e0 = t * TILE_E;
   const int nv = (int)(nnz - e0 < TILE_E ? nnz - e0 : TILE_E);  // entries in the tile, >= 1
-  int32_t* rw = rid[w];
 #pragma unroll
   for (int s = 0; s < TILE_S; ++s) rw[s * WAVE + l] = -1;
   const int32_t r0 = tstart[t], r1 = tstart[t + 1], rc = tcont[t];
@@ -650,6 +649,20 @@ __global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, c
   }
   issue_fence();
   wave_tile_reduce<T, false>(t, nv, rr, cc, vv, rprev, rnext, x, y, head_part, tail_part, tail_row, tinfo);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                  const int32_t* __restrict__ tstart, const int32_t* __restrict__ tcont,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  double* __restrict__ head_part, double* __restrict__ tail_part,
+                                                  int32_t* __restrict__ tail_row, int32_t* __restrict__ tinfo) {
+  __shared__ int32_t rid[BS / WAVE][TILE_E];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int64_t t = (int64_t)blockIdx.x * (BS / WAVE) + w;
+  if (t >= ntiles) return;
+  csr_tile<T>(t, nnz, ntiles, ptr, col, val, tstart, tcont, x, y, head_part, tail_part, tail_row, tinfo, rid[w]);
 }
 
 spmv_status_t csr_build_tiles(spmv_mat_s* A, hipStream_t s) {
@@ -884,11 +897,29 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
 // the matrices, no dependent row-pointer loads).  A SELL-C-sigma matrix
 // contributes items of 256 / C chunks (one stored row per thread).
 struct BatchItem {
-  const void* p0;  // CSR: ptr; SELL: cs (chunk slot offsets)
+  const void* p0;  // CSR: ptr; SELL: cs (chunk slot offsets); CSR wave tiles: its BatchTiles record
   const int32_t* col;
   const void* val;
   const int32_t* perm;  // SELL with sigma > 1: stored row -> row (else null)
-  int32_t kind, m, r0, r1, k0, k1, logc, M;  // kind 0: CSR rows [r0, r1), entries [k0, k1); 1: SELL chunks [r0, r1)
+  // kind 0: CSR rows [r0, r1), entries [k0, k1); 1: SELL chunks [r0, r1);
+  // 2: CSR wave tiles [r0, r1), at most one per wave of the workgroup
+  int32_t kind, m, r0, r1, k0, k1, logc, M;
+};
+
+// A CSR handle built with wave tiles (SPMV_FLAG_CSR_TILES): its arrays and
+// tile tables, and its index m in the batch (for the fix-up pass).
+struct BatchTiles {
+  const int32_t* ptr;
+  const int32_t* col;
+  const void* val;
+  const int32_t* tstart;
+  const int32_t* tcont;
+  double* head;
+  double* tail;
+  int32_t* trow;
+  int32_t* info;
+  int64_t nnz, ntiles;
+  int32_t m, pad;
 };
 
 __global__ void k_batch_items(int64_t nblk, const int32_t* __restrict__ blk_row, const int32_t* __restrict__ ptr,
@@ -987,14 +1018,89 @@ __global__ __launch_bounds__(BS) void k_csr_batched(int64_t nitems, const BatchI
     sell_item<T>(it, (const T*)xs[it.m], (T*)ys[it.m]);
     return;
   }
+  if (it.kind == 2) {  // one wave per tile; the row tables alias the staging area
+    static_assert(sizeof(prod) >= sizeof(int32_t) * (BS / WAVE) * TILE_E, "tile row tables exceed the LDS area");
+    const BatchTiles* d = (const BatchTiles*)it.p0;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int64_t t = (int64_t)it.r0 + w;
+    if (t >= it.r1) return;
+    csr_tile<T>(t, d->nnz, d->ntiles, d->ptr, d->col, (const T*)d->val, d->tstart, d->tcont, (const T*)xs[it.m],
+                (T*)ys[it.m], d->head, d->tail, d->trow, d->info, reinterpret_cast<int32_t*>(prod) + w * TILE_E);
+    return;
+  }
   csr_rows_block<T>(it.r0, it.r1, it.k0, it.k1, (const int32_t*)it.p0, it.col, (const T*)it.val,
                     (const T*)xs[it.m], (T*)ys[it.m], prod, sptr);
 }
 
-// Items of matrix A (index m of the batch): CSR row blocks or SELL chunk groups.
+// The wave-tile matrices' crossing rows, after the batched launch: one
+// workgroup per matrix, each tile whose last row continues sums that row's
+// partials in tile order (as k_tile_fix does for one matrix).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_batch_tile_fix(const BatchTiles* __restrict__ d, void* const* __restrict__ ys) {
+  const BatchTiles b = d[blockIdx.x];
+  T* y = (T*)ys[b.m];
+  for (int64_t t = threadIdx.x; t < b.ntiles; t += BS) {
+    if (b.info[t] != TILE_TAIL) continue;
+    double tot = b.tail[t];
+    for (int64_t u = t + 1;; ++u) {
+      tot += b.head[u];
+      if (b.info[u] != TILE_SPAN) break;
+    }
+    y[b.trow[t]] = (T)tot;
+  }
+}
+
+// Items of matrix A (index m of the batch): CSR row blocks, CSR wave tiles
+// (handles built with them) or SELL chunk groups.
 int64_t batch_item_count(const spmv_mat_s* A) {
   if (A->fmt == SPMV_FMT_SELL) return cdiv(A->nchunks, BS / A->C);
+  if (A->ntiles_csr > 0) return cdiv(A->ntiles_csr, BS / WAVE);
   return A->nblk;
+}
+
+size_t batch_tiles_size() { return sizeof(BatchTiles); }
+
+// The tile record of matrix A (host) and its items (written to the device at
+// items, referring to the record at dev_rec).
+spmv_status_t batch_tile_items(const spmv_mat_s* A, int32_t m, void* host_rec, const void* dev_rec, void* items,
+                               hipStream_t s) {
+  BatchTiles b;
+  b.ptr = A->ptr;
+  b.col = A->col;
+  b.val = A->val;
+  b.tstart = A->ct_start;
+  b.tcont = A->ct_cont;
+  b.head = A->ct_head;
+  b.tail = A->ct_tail;
+  b.trow = A->ct_trow;
+  b.info = A->ct_info;
+  b.nnz = A->nnz;
+  b.ntiles = A->ntiles_csr;
+  b.m = m;
+  b.pad = 0;
+  memcpy(host_rec, &b, sizeof(b));
+  const int64_t n = batch_item_count(A);
+  std::vector<BatchItem> v((size_t)n);
+  for (int64_t j = 0; j < n; ++j) {
+    BatchItem& it = v[(size_t)j];
+    memset(&it, 0, sizeof(it));
+    it.p0 = dev_rec;
+    it.kind = 2;
+    it.m = m;
+    it.r0 = (int32_t)(j * (BS / WAVE));
+    it.r1 = (int32_t)std::min<int64_t>(A->ntiles_csr, (j + 1) * (BS / WAVE));
+  }
+  SPMV_HIP(hipMemcpyAsync(items, v.data(), sizeof(BatchItem) * (size_t)n, hipMemcpyHostToDevice, s));
+  SPMV_HIP(hipStreamSynchronize(s));  // v is freed on return
+  return SPMV_OK;
+}
+
+spmv_status_t launch_batch_tile_fix(int dt, int32_t ntm, const void* recs, void* const* ys, hipStream_t s) {
+  if (ntm <= 0) return SPMV_OK;
+  if (dt == SPMV_F64) launch(k_batch_tile_fix<double>, ntm, BS, s, (const BatchTiles*)recs, ys);
+  else launch(k_batch_tile_fix<float>, ntm, BS, s, (const BatchTiles*)recs, ys);
+  SPMV_LAUNCH_CHECK();
+  return SPMV_OK;
 }
 
 spmv_status_t batch_items_fill(const spmv_mat_s* A, int32_t m, void* items, hipStream_t s) {

@@ -108,20 +108,27 @@ SELL_PARAMS = [dict(sell_C=64, sell_sigma=1), dict(sell_C=64, sell_sigma=1 << 30
 
 @pytest.mark.parametrize("dt", [0, 1])
 def test_mixed_csr_sell_batch_matches_per_matrix_oracle(torch, dt):
-    """One launch over CSR row blocks and SELL-C-sigma chunk groups of several
-    C and sigma (sorted and unsorted, chunks wider than 8 slots, rows of
-    thousands of entries, an empty matrix): every matrix meets the bar."""
+    """One launch over CSR row blocks, CSR wave tiles (with the fix-up pass
+    for rows crossing tiles) and SELL-C-sigma chunk groups of several C and
+    sigma (sorted and unsorted, chunks wider than 8 slots, rows of thousands
+    of entries, an empty matrix): every matrix meets the bar."""
     specs = synth.batch_specs(20, seed=18, rows_lo=100, rows_hi=30_000)
     mats = [synth.make(s) for s in specs]
     mats.append(synth.zipf_rows(4000, 5000, 2.0, 16, 3000, 3, 4))
     mats.append(synth.from_dense(np.zeros((33, 9))))
     mats.append(synth.laplace2d(20))
+    mats.append(synth.from_dense(np.zeros((40, 7))))
+    mats.append(synth.laplace2d(9))
+    mats.append(synth.zipf_rows(6000, 6000, 2.0, 24, 5000, 5, 6))  # index 25, as wave tiles: rows across tiles
     handles, keep, xs, ys, refs = [], [], [], [], []
     for i, A in enumerate(mats):
         val = A.val.astype(np.float32) if dt == 1 else A.val
         base = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt)
-        if i % 3 == 2:
+        if i % 4 == 2:
             handles.append(base)
+        elif i % 4 == 1:
+            keep.append(base)
+            handles.append(base.convert("csr", flags=32))  # wave tiles
         else:
             keep.append(base)
             handles.append(base.convert("sell", **SELL_PARAMS[i % len(SELL_PARAMS)]))
@@ -132,6 +139,7 @@ def test_mixed_csr_sell_batch_matches_per_matrix_oracle(torch, dt):
         ys.append(torch.full((A.M,), float("nan"), dtype=S.torch_dtype(dt), device="cuda"))
         refs.append(reference(A, x64, dt))
     assert {h.fmt for h in handles} == {"csr", "sell"}
+    assert handles[25].params["flags"] & 32 and handles[21].params["flags"] & 32  # tiles; 21 has no entries
     B = S.Batch(handles)
     for rep in range(2):
         B.run(xs, ys)
