@@ -170,3 +170,21 @@ def test_auto_for_calls_keeps_csr_for_few_calls(torch, trained):
         assert d1["t_convert_ms"] > 0
     yref, den = reference(A, synth.vector(A.N, 33), 0)
     assert rowwise_err(Bn.run(x).cpu().numpy(), yref, den) <= TOL[0]
+
+
+def test_deployed_models_decide_the_benchmark_matrices(torch):
+    """The models shipped in data/ cover the benchmark's 100^3 27-point
+    stencil and its Zipf matrix (features inside the training range), so
+    selection there is one feature pass and one inference, not the
+    exhaustive fallback; the stencil's pick is a regular-row format."""
+    from paper_1805_11938_amd import workloads as W
+    for name, want in (("stencil27_100", ("sell", "ell", "hyb")), ("zipf_1M", None)):
+        A = W.make(name)
+        for dname, dt in (("f64", S.F64), ("f32", S.F32)):
+            m = S.Model.load(SEL.model_path(dname))
+            Ad = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, A.val.astype(np.float32) if dt == S.F32 else A.val, dt)
+            assert SEL.in_domain(Ad, m), (name, dname, SEL.scaled_features(Ad, m))
+            fmt, _ = SEL.choose(Ad, m)
+            if want:
+                assert fmt in want, (name, dname, fmt)
+            del Ad

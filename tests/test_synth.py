@@ -55,3 +55,33 @@ def test_selector_specs_cover_generators_and_ranges():
 def test_batch_specs():
     specs = synth.batch_specs(16)
     assert len(specs) == 16 and all(1e3 <= s["M"] <= 2e5 for s in specs)
+
+
+def test_large_selector_specs_span_the_benchmark_shapes():
+    """Matrices 3000.. of the selector set: 3-D stencils, banded, uniform,
+    Zipf and R-MAT with 2x10^7..3x10^8 expected nonzeros and up to 1.7x10^7
+    rows, so the benchmark matrices (the 100^3 stencil: 10^6 rows, 2.6x10^7
+    nonzeros; R-MAT scale 24) lie inside the training range."""
+    specs = [synth.selector_spec(i) for i in range(synth.N_BASE, synth.N_BASE + 40)]
+    assert [s["kind"] for s in specs[:5]] == list(synth.LARGE_KINDS)
+    assert all(s["kind"] in synth.LARGE_KINDS for s in specs)
+    for s in specs:
+        p = s["params"]
+        if s["kind"] == "stencil27":
+            assert 100 <= p["n"] <= 220 and s["M"] == p["n"] ** 3
+            nnz = 27 * p["n"] ** 3
+        elif s["kind"] == "rmat":
+            assert 20 <= p["scale"] <= 24 and s["M"] == 1 << p["scale"]
+            nnz = s["M"] * p["edge_factor"] * 0.9
+        elif s["kind"] == "banded":
+            nnz = s["M"] * (1 + 2 * p["halfwidth"] * p["fill"])
+        else:
+            nnz = s["M"] * p["mean"]
+        assert 1e6 <= s["M"] <= 1.7e7 and nnz <= 3.3e8, s
+        if s["kind"] != "stencil27":
+            assert nnz >= 2e7, s
+    assert specs == [synth.selector_spec(i) for i in range(synth.N_BASE, synth.N_BASE + 40)]
+    # the base set is unchanged by the extension
+    assert synth.selector_spec(5) == synth.selector_specs(6)[5]
+    small = synth.make(dict(index=0, kind="stencil27", M=8, seed=3, params=dict(n=2)))
+    assert small.M == 8 and small.nnz == 64  # every pair of the 2x2x2 grid is a neighbour
