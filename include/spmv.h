@@ -75,8 +75,11 @@ typedef struct {
   uint32_t flags;            /* SPMV_FLAG_* */
   int32_t bands;             /* CSR, SELL and CSR5: split the columns into this many equal bands (1..64), each
                                 converted to the format on its own over all M rows and run one after
-                                another, so each launch gathers from one slice of x that fits the L2; the
-                                band products are added in band order (FP64) by a final pass.  HYB: the
+                                another, so each launch gathers from one slice of x that fits the L2; band 0
+                                writes y and each later band adds its row sums onto y (in FP64, rounded once
+                                per band), so the bands are summed in band order.  CSR over bands: row
+                                blocks, wave tiles or V lanes per row (SPMV_FLAG_CSR_WAVES or
+                                SPMV_FLAG_CSR_BANDS -> UNSUPPORTED).  HYB: the
                                 COO tail is ordered by band (then row, column) and each band's pass adds
                                 onto y after the previous one.  0 or 1 = no split (default); ELL returns
                                 UNSUPPORTED for bands > 1 */

@@ -4,8 +4,9 @@
 // columns) and the bands run one after another.  Each launch then gathers
 // from one slice of x, which fits an XCD's L2 when x itself does not, and
 // random gathers served from L2 cost about half of those served from the
-// Infinity Cache.  Band b writes its product into row b of an M x nb scratch
-// in the value type; a last pass adds the bands in band order (in FP64).
+// Infinity Cache.  Band 0 writes y; every later band adds its product onto
+// y (each row's band sum added in FP64, rounded once per band), so the
+// bands are summed in band order with no scratch and no summing pass.
 #include "common.h"
 
 namespace spmv {
@@ -17,20 +18,13 @@ static unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, BS), 1 << 20));
 }
 
-template <typename T>
-__global__ void k_band_sum(int64_t M, int nb, const T* __restrict__ part, T* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += (double)part[(int64_t)b * M + i];
-    y[i] = (T)s;
-  }
-}
-
 spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   const int nb = A->params.bands;
   if (A->fmt != SPMV_FMT_SELL && A->fmt != SPMV_FMT_CSR5 && A->fmt != SPMV_FMT_CSR)
     return fail(SPMV_ERR_UNSUPPORTED, "column bands are implemented for CSR, SELL and CSR5");
   if (nb > 64) return fail(SPMV_ERR_UNSUPPORTED, "%d column bands (at most 64)", nb);
+  if (A->fmt == SPMV_FMT_CSR && (A->params.flags & (SPMV_FLAG_CSR_WAVES | SPMV_FLAG_CSR_BANDS)))
+    return fail(SPMV_ERR_UNSUPPORTED, "CSR over column bands runs as row blocks, wave tiles or V lanes per row");
   const int64_t M = src->M, N = src->N, sv = A->sv;
   const int64_t bw = std::max<int64_t>(1, cdiv(N, nb));
   A->band_w = bw;
@@ -62,6 +56,7 @@ spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     sub->nnz = band.nnz;
     sub->params = A->params;
     sub->params.bands = 1;
+    sub->acc = b > 0;  // bands after the first add onto y
     const spmv_status_t st = A->fmt == SPMV_FMT_SELL   ? convert_sell(&band, sub.get(), s)
                              : A->fmt == SPMV_FMT_CSR5 ? convert_csr5(&band, sub.get(), s)
                                                        : convert_csr(&band, sub.get(), s);
@@ -79,27 +74,19 @@ spmv_status_t convert_banded(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     A->sub.push_back(std::move(sub));
   }
   const int64_t cap = A->params.max_bytes > 0 ? A->params.max_bytes : default_max_bytes();
-  if (fmt_bytes + (int64_t)nb * M * sv > cap)
-    return fail(SPMV_ERR_TOO_LARGE, "%d column bands need %lld bytes (cap %lld)", nb,
-                (long long)(fmt_bytes + (int64_t)nb * M * sv), (long long)cap);
-  SPMV_TRY(mat_alloc(A, &A->spart, (size_t)sv * nb * std::max<int64_t>(M, 1)));
-  // the bands' arrays, x once, y once (the band products in the scratch are
-  // traffic of this execution layout, not of the product: not counted)
+  if (fmt_bytes > cap)
+    return fail(SPMV_ERR_TOO_LARGE, "%d column bands need %lld bytes (cap %lld)", nb, (long long)fmt_bytes,
+                (long long)cap);
+  // the bands' arrays, x once, y once (y read and written again by each band
+  // after the first is traffic of this execution layout, not of the product:
+  // not counted)
   A->bytes_fmt = fmt_bytes + N * sv + M * sv;
   SPMV_HIP(hipStreamSynchronize(s));
   return SPMV_OK;
 }
 
 spmv_status_t run_banded(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
-  const int nb = (int)A->sub.size();
-  const int64_t M = A->M;
-  for (int b = 0; b < nb; ++b)
-    SPMV_TRY(dispatch_run(A->sub[b].get(), x, (char*)A->spart + (size_t)A->sv * b * M, s));
-  if (A->dt == SPMV_F64)
-    launch(k_band_sum<double>, grid_for(M), BS, s, M, nb, (const double*)A->spart, (double*)y);
-  else
-    launch(k_band_sum<float>, grid_for(M), BS, s, M, nb, (const float*)A->spart, (float*)y);
-  SPMV_LAUNCH_CHECK();
+  for (const auto& b : A->sub) SPMV_TRY(dispatch_run(b.get(), x, y, s));  // in band order on one stream
   return SPMV_OK;
 }
 

@@ -211,7 +211,7 @@ struct spmv_mat_s {
   // format built from the entries with col in [b*band_w, (b+1)*band_w), over
   // all M rows; this handle holds no format arrays of its own
   std::vector<std::unique_ptr<spmv_mat_s>> sub;
-  void* spart = nullptr;  // bands x M band products in the value type (run scratch)
+  int32_t acc = 0;  // a column band after the first: its run adds its product onto y instead of writing it
 
   int64_t bytes_fmt = 0, pad_slots = 0;
 
@@ -297,6 +297,13 @@ __device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
 template <typename T>
 __device__ __forceinline__ T ldnt32(const T* base, uint32_t idx) {
   return __builtin_nontemporal_load((const T*)((const char*)base + idx * (uint32_t)sizeof(T)));
+}
+
+// y[i] = s, or y[i] + s (rounded once to the value type) when add is set --
+// the runs of column bands after the first add onto the previous bands' sum.
+template <typename TY>
+__device__ __forceinline__ void put_y(TY* y, int64_t i, double s, int add) {
+  y[i] = add ? (TY)((double)y[i] + s) : (TY)s;
 }
 
 // Keeps the compiler from moving work across this point: used after a batch

@@ -173,7 +173,7 @@ template <typename T, typename TY>
 __device__ __forceinline__ void csr_rows_staged(int64_t r0, int64_t r1, int64_t k0, int64_t k1,
                                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                 const T* __restrict__ val, const T* __restrict__ x,
-                                                TY* __restrict__ y, double* prod, int32_t* sptr) {
+                                                TY* __restrict__ y, double* prod, int32_t* sptr, int add) {
   const int t = threadIdx.x;
   const int64_t E = k1 - k0, nr = r1 - r0;
   const bool staged = nr <= CSR_RCAP;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void csr_rows_staged(int64_t r0, int64_t r1, int64_t 
     double s = 0.0;
     for (int k = a + lane; k < e; k += V) s += prod[k];
     s = group_sum_rt(s, V);
-    if (lane == 0) y[r0 + r] = (TY)s;
+    if (lane == 0) put_y(y, r0 + r, s, add);
   }
   __syncthreads();  // prod / sptr may be reused by the caller's next block
 }
@@ -225,10 +225,10 @@ __device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, int64_t k
                                                const int32_t* __restrict__ ptr,
                                                const int32_t* __restrict__ col, const T* __restrict__ val,
                                                const T* __restrict__ x, TY* __restrict__ y, double* prod,
-                                               int32_t* sptr) {
+                                               int32_t* sptr, int add = 0) {
   if (r0 >= r1) return;
   if (k1 - k0 <= CSR_CAP) {
-    csr_rows_staged<T, TY>(r0, r1, k0, k1, ptr, col, val, x, y, prod, sptr);
+    csr_rows_staged<T, TY>(r0, r1, k0, k1, ptr, col, val, x, y, prod, sptr, add);
     return;
   }
   int64_t lo = r0 + 1, hi = r1;  // first r with ptr[r] - k0 > CSR_CAP (ptr[r1] qualifies)
@@ -238,20 +238,20 @@ __device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, int64_t k
     else lo = mid + 1;
   }
   const int64_t rl = lo - 1;  // rows [r0, rl) fit the staging
-  if (rl > r0) csr_rows_staged<T, TY>(r0, rl, k0, ptr[rl], ptr, col, val, x, y, prod, sptr);
+  if (rl > r0) csr_rows_staged<T, TY>(r0, rl, k0, ptr[rl], ptr, col, val, x, y, prod, sptr, add);
   const int t = threadIdx.x;
   const int w = t / WAVE, lane = __lane_id();
   for (int64_t r = rl + w; r < r1; r += BS / WAVE) {
     const int64_t a = ptr[r], e = ptr[r + 1];
     if (e - a >= CSR_LONG) continue;
     double s = group_sum<64>(row_dot(col, val, x, a, e, lane, WAVE));
-    if (lane == 0) y[r] = (TY)s;
+    if (lane == 0) put_y(y, r, s, add);
   }
   for (int64_t r = rl; r < r1; ++r) {
     const int64_t a = ptr[r], e = ptr[r + 1];
     if (e - a < CSR_LONG) continue;
     const double s = block_sum(row_dot(col, val, x, a, e, t, BS), prod);
-    if (t == 0) y[r] = (TY)s;
+    if (t == 0) put_y(y, r, s, add);
   }
   __syncthreads();
 }
@@ -259,13 +259,14 @@ __device__ __forceinline__ void csr_rows_block(int64_t r0, int64_t r1, int64_t k
 template <typename T, bool XCD>
 __global__ __launch_bounds__(BS) void k_csr_rows(int64_t nblk, const int32_t* __restrict__ blk_row,
                                                  const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                                 const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
+                                                 const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
+                                                 int add) {
   __shared__ double prod[CSR_CAP];
   __shared__ int32_t sptr[CSR_RCAP + 1];
   const uint32_t b = XCD ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   if (b >= nblk) return;
   const int64_t r0 = blk_row[b], r1 = blk_row[b + 1];
-  csr_rows_block<T>(r0, r1, ptr[r0], ptr[r1], ptr, col, val, x, y, prod, sptr);
+  csr_rows_block<T>(r0, r1, ptr[r0], ptr[r1], ptr, col, val, x, y, prod, sptr, add);
 }
 
 // ------------------------------------------------------- column bands
@@ -559,12 +560,12 @@ __global__ __launch_bounds__(BS) void k_csr_long_fix(int64_t nlong, const int4* 
 template <typename T, int V>
 __global__ __launch_bounds__(BS) void k_csr_vector(int64_t M, const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ x, T* __restrict__ y) {
+                                                   const T* __restrict__ x, T* __restrict__ y, int add) {
   const int64_t r = (int64_t)blockIdx.x * (BS / V) + threadIdx.x / V;
   const int lane = threadIdx.x % V;
   if (r >= M) return;  // uniform across the V-lane group
   const double s = group_sum<V>(row_dot(col, val, x, ptr[r], ptr[r + 1], lane, V));
-  if (lane == 0) y[r] = (T)s;
+  if (lane == 0) put_y(y, r, s, add);
 }
 
 // ------------------------------------------------------------ wave tiles
@@ -605,7 +606,7 @@ __global__ void k_csr_tile_rows(int64_t M, int64_t nnz, int64_t ntiles, const in
 
 // One tile t of a CSR (entries [t*TILE_E, ...) of col / val) by one wave:
 // rows marked in the wave's LDS table rw, then the segmented reduction.
-template <typename T>
+template <typename T, bool ADD = false>
 __device__ __forceinline__ void csr_tile(int64_t t, int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
                                          const int32_t* __restrict__ col, const T* __restrict__ val,
                                          const int32_t* __restrict__ tstart, const int32_t* __restrict__ tcont,
@@ -626,7 +627,7 @@ __device__ __forceinline__ void csr_tile(int64_t t, int64_t nnz, int64_t ntiles,
   for (int64_t r = r0 + l; r < r1; r += WAVE) {  // rows starting in the tile
     const int32_t a = ptr[r], b = ptr[r + 1];
     if (b > a) rw[a - e0] = (int32_t)r;
-    else y[r] = (T)0;
+    else if (!ADD) y[r] = (T)0;  // an empty row (adding nothing onto y when ADD)
   }
   int32_t cc[TILE_S], rr[TILE_S];
   T vv[TILE_S];
@@ -648,10 +649,10 @@ __device__ __forceinline__ void csr_tile(int64_t t, int64_t nnz, int64_t ntiles,
     rr[s] = s * WAVE + l < nv ? v : TILE_NONE;
   }
   issue_fence();
-  wave_tile_reduce<T, false>(t, nv, rr, cc, vv, rprev, rnext, x, y, head_part, tail_part, tail_row, tinfo);
+  wave_tile_reduce<T, ADD>(t, nv, rr, cc, vv, rprev, rnext, x, y, head_part, tail_part, tail_row, tinfo);
 }
 
-template <typename T>
+template <typename T, bool ADD>
 __global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
                                                   const int32_t* __restrict__ tstart, const int32_t* __restrict__ tcont,
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(BS) void k_csr_tiles(int64_t nnz, int64_t ntiles, c
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int64_t t = (int64_t)blockIdx.x * (BS / WAVE) + w;
   if (t >= ntiles) return;
-  csr_tile<T>(t, nnz, ntiles, ptr, col, val, tstart, tcont, x, y, head_part, tail_part, tail_row, tinfo, rid[w]);
+  csr_tile<T, ADD>(t, nnz, ntiles, ptr, col, val, tstart, tcont, x, y, head_part, tail_part, tail_row, tinfo, rid[w]);
 }
 
 spmv_status_t csr_build_tiles(spmv_mat_s* A, hipStream_t s) {
@@ -690,22 +691,31 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   if (V == 0 && A->nbands > 0) return run_csr_bands<T>(A, x, y, s);
   if (V == 0 && A->ntiles_csr > 0) {
     const int64_t nt = A->ntiles_csr;
-    launch(k_csr_tiles<T>, (unsigned)cdiv(nt, BS / WAVE), BS, s, A->nnz, nt, ptr, A->col, val, A->ct_start, A->ct_cont,
-           x, y, A->ct_head, A->ct_tail, A->ct_trow, A->ct_info);
+    const unsigned g = (unsigned)cdiv(nt, BS / WAVE), gf = (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096);
+    if (A->acc)
+      launch(k_csr_tiles<T, true>, g, BS, s, A->nnz, nt, ptr, A->col, val, A->ct_start, A->ct_cont, x, y, A->ct_head,
+             A->ct_tail, A->ct_trow, A->ct_info);
+    else
+      launch(k_csr_tiles<T, false>, g, BS, s, A->nnz, nt, ptr, A->col, val, A->ct_start, A->ct_cont, x, y, A->ct_head,
+             A->ct_tail, A->ct_trow, A->ct_info);
     SPMV_LAUNCH_CHECK();
-    if (nt > 1)
-      launch(k_tile_fix<T, false>, (unsigned)std::min<int64_t>(cdiv(nt, BS), 4096), BS, s, nt,
-             (const double*)A->ct_head, (const double*)A->ct_tail, (const int32_t*)A->ct_trow,
-             (const int32_t*)A->ct_info, y);
+    if (nt > 1) {
+      if (A->acc)
+        launch(k_tile_fix<T, true>, gf, BS, s, nt, (const double*)A->ct_head, (const double*)A->ct_tail,
+               (const int32_t*)A->ct_trow, (const int32_t*)A->ct_info, y);
+      else
+        launch(k_tile_fix<T, false>, gf, BS, s, nt, (const double*)A->ct_head, (const double*)A->ct_tail,
+               (const int32_t*)A->ct_trow, (const int32_t*)A->ct_info, y);
+    }
     SPMV_LAUNCH_CHECK();
     return SPMV_OK;
   }
   if (V == 0) {
     if (!(A->params.flags & SPMV_FLAG_CSR_WAVES)) {
       if (A->params.flags & SPMV_FLAG_LINEAR)
-        launch(k_csr_rows<T, false>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y);
+        launch(k_csr_rows<T, false>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y, A->acc);
       else
-        launch(k_csr_rows<T, true>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y);
+        launch(k_csr_rows<T, true>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, ptr, A->col, val, x, y, A->acc);
     } else
     {
       const unsigned g = (unsigned)std::min<int64_t>(cdiv(A->nunits + A->nseg, BS / WAVE), resident_blocks(8));
@@ -719,13 +729,13 @@ static spmv_status_t run_csr_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) {
   } else {
     const unsigned g = (unsigned)cdiv(A->M, BS / V);
     switch (V) {
-      case 1: launch(k_csr_vector<T, 1>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
-      case 2: launch(k_csr_vector<T, 2>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
-      case 4: launch(k_csr_vector<T, 4>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
-      case 8: launch(k_csr_vector<T, 8>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
-      case 16: launch(k_csr_vector<T, 16>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
-      case 32: launch(k_csr_vector<T, 32>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
-      case 64: launch(k_csr_vector<T, 64>, g, BS, s, A->M, ptr, A->col, val, x, y); break;
+      case 1: launch(k_csr_vector<T, 1>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
+      case 2: launch(k_csr_vector<T, 2>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
+      case 4: launch(k_csr_vector<T, 4>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
+      case 8: launch(k_csr_vector<T, 8>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
+      case 16: launch(k_csr_vector<T, 16>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
+      case 32: launch(k_csr_vector<T, 32>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
+      case 64: launch(k_csr_vector<T, 64>, g, BS, s, A->M, ptr, A->col, val, x, y, A->acc); break;
       default: return fail(SPMV_ERR_UNSUPPORTED, "csr_lanes_per_row must be 0 or a power of two <= 64 (got %d)", V);
     }
   }

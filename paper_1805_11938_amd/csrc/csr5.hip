@@ -316,6 +316,7 @@ struct C5Args {
   const int32_t* nzbase;
   int32_t tail_rlo, tail_row;
   double* carry;
+  int add;  // add the rows' sums onto y (a column band after the first)
 };
 
 template <typename T, bool EMPTY>
@@ -326,10 +327,10 @@ __device__ __forceinline__ void c5_write(const C5Args& a, int64_t t, int64_t row
     return;
   }
   if (!EMPTY) {
-    y[row0 + j] = (T)s;
+    put_y(y, row0 + j, s, a.add);
     return;
   }
-  y[a.nzrow[nzb + j]] = (T)s;  // empty rows are zeroed by k_c5_zero
+  put_y(y, a.nzrow[nzb + j], s, a.add);  // empty rows are zeroed by k_c5_zero (left alone when adding)
 }
 
 // The tail (entries past the last full tile) in CSR order.  Its leading
@@ -351,7 +352,7 @@ __device__ void c5_tail(const C5Args& a, const T* __restrict__ val, const T* __r
   const int64_t nw = (int64_t)gridDim.x * (BS / WAVE);
   for (int64_t r = a.tail_rlo + (int64_t)blockIdx.x * (BS / WAVE) + t / WAVE; r < a.M; r += nw) {
     const double s = group_sum<64>(row_dot(a.col, val, x, a.ptr[r], a.ptr[r + 1], lane, WAVE));
-    if (lane == 0) y[r] = (T)s;
+    if (lane == 0) put_y(y, r, s, a.add);
   }
 }
 
@@ -502,10 +503,11 @@ static spmv_status_t run_csr5_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) 
   a.tail_rlo = A->tail_rlo;
   a.tail_row = A->c5_tail_row;
   a.carry = A->carry;
+  a.add = A->acc;
   // one workgroup per BS / omega tiles: the dispatcher balances them (a
   // persistent grid of 8 workgroups per CU was 4% slower on the stencil)
   const unsigned grid = (unsigned)std::max<int64_t>(1, a.nb_main);
-  if (A->nerows > 0) {
+  if (A->nerows > 0 && !A->acc) {
     launch(k_c5_zero<T>, (unsigned)std::min<int64_t>(cdiv(A->nerows, BS), 4096), BS, s, A->nerows, A->erows, y);
     SPMV_LAUNCH_CHECK();
   }

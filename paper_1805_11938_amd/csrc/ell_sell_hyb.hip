@@ -517,7 +517,7 @@ template <typename T, int LOGC, bool PERM, int KC>
 __global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t c0, int64_t nchunks, const int64_t* __restrict__ cs,
                                                   const int32_t* __restrict__ perm, const int32_t* __restrict__ scol,
                                                   const T* __restrict__ sval, const T* __restrict__ x,
-                                                  T* __restrict__ y, int remap) {
+                                                  T* __restrict__ y, int remap, int add) {
   constexpr int C = 1 << LOGC;
   // one wave per workgroup (the finest unit the dispatcher balances).  With
   // remap each XCD takes a contiguous range of chunks (neighbouring rows
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t c0, int64_t
   }
   const int64_t pos = c * C + p;
   const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-  if (r >= 0) y[r] = (T)((sa[0] + sa[1]) + (sa[2] + sa[3]));
+  if (r >= 0) put_y(y, r, (sa[0] + sa[1]) + (sa[2] + sa[3]), add);
 }
 
 // Narrow SELL with C = 64, four waves per chunk: wave h takes the slots
@@ -554,7 +554,8 @@ template <typename T, bool PERM, int KC>
 __global__ __launch_bounds__(4 * WAVE) void k_sell_kc4(int64_t M, int64_t c0, int64_t nchunks,
                                                       const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ scol, const T* __restrict__ sval,
-                                                      const T* __restrict__ x, T* __restrict__ y, int remap) {
+                                                      const T* __restrict__ x, T* __restrict__ y, int remap,
+                                                      int add) {
   constexpr int KQ = (KC + 3) / 4;
   __shared__ double part[4][WAVE];
   const int h = (int)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(4 * WAVE) void k_sell_kc4(int64_t M, int64_t c0, in
   if (h == 0) {
     const int64_t pos = c * WAVE + p;
     const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-    if (r >= 0) y[r] = (T)(((part[0][p] + part[1][p]) + part[2][p]) + part[3][p]);
+    if (r >= 0) put_y(y, r, ((part[0][p] + part[1][p]) + part[2][p]) + part[3][p], add);
   }
 }
 
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
                                                      const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
                                                      const int32_t* __restrict__ scol, const T* __restrict__ sval,
                                                      const T* __restrict__ x, T* __restrict__ y,
-                                                     double* __restrict__ part, int remap) {
+                                                     double* __restrict__ part, int remap, int add) {
   constexpr int C = 1 << LOGC;
   double sa[4] = {0.0, 0.0, 0.0, 0.0};
   if ((int64_t)blockIdx.x < nwg_wide) {
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
     if (w <= SELL_KT) {
       const int64_t pos = c * C + p;
       const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-      if (r >= 0) y[r] = (T)s;
+      if (r >= 0) put_y(y, r, s, add);
     } else {
       part[it * C + p] = s;
     }
@@ -651,13 +652,14 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
   }
   const int64_t pos = c * C + p;
   const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-  if (r >= 0) y[r] = (T)((sa[0] + sa[1]) + (sa[2] + sa[3]));
+  if (r >= 0) put_y(y, r, (sa[0] + sa[1]) + (sa[2] + sa[3]), add);
 }
 
 // one thread per (wide chunk, stored row): y = sum of the slices' partials in order
 template <typename T, bool PERM>
 __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restrict__ wide,
-                           const int32_t* __restrict__ perm, const double* __restrict__ part, T* __restrict__ y) {
+                           const int32_t* __restrict__ perm, const double* __restrict__ part, T* __restrict__ y,
+                           int add) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t wi = gid / C;
   if (wi >= nwide) return;
@@ -679,7 +681,7 @@ __global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restri
   const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   const int64_t pos = (int64_t)wd.x * C + p;
   const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-  if (r >= 0) y[r] = (T)s;
+  if (r >= 0) put_y(y, r, s, add);
 }
 
 template <typename T, int LOGC, int KC>
@@ -690,10 +692,10 @@ static void launch_sell_mixed(spmv_mat_s* A, const void* x, void* y, hipStream_t
   const unsigned g = (unsigned)(nwide + nnarrow);
   if (A->perm)
     launch(k_sell_mixed<T, LOGC, true, KC>, g, WAVE, s, A->M, A->nitems, A->items, nwide, A->kc_first, A->nchunks,
-           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap);
+           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap, A->acc);
   else
     launch(k_sell_mixed<T, LOGC, false, KC>, g, WAVE, s, A->M, A->nitems, A->items, nwide, A->kc_first, A->nchunks,
-           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap);
+           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap, A->acc);
 }
 
 template <typename T, int LOGC, int KC>
@@ -709,18 +711,18 @@ static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s)
   if (LOGC == 6 && (A->params.flags & SPMV_FLAG_SPLIT4)) {  // g = one workgroup per chunk
     if (A->perm)
       launch(k_sell_kc4<T, true, KC>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
-             (const T*)A->sval, (const T*)x, (T*)y, remap);
+             (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
     else
       launch(k_sell_kc4<T, false, KC>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
-             (const T*)A->sval, (const T*)x, (T*)y, remap);
+             (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
     return;
   }
   if (A->perm)
     launch(k_sell_kc<T, LOGC, true, KC>, g, WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
-           (const T*)A->sval, (const T*)x, (T*)y, remap);
+           (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
   else
     launch(k_sell_kc<T, LOGC, false, KC>, g, WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
-           (const T*)A->sval, (const T*)x, (T*)y, remap);
+           (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
 }
 
 // Chunks [kc_first, nchunks) (at most SELL_KC_MAX wide) go through the one-pass
@@ -775,9 +777,9 @@ static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) 
   if (A->nwide > 0) {
     const unsigned gf = (unsigned)cdiv(A->nwide << LOGC, BS);
     if (A->perm)
-      launch(k_sell_fix<T, true>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
+      launch(k_sell_fix<T, true>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y, A->acc);
     else
-      launch(k_sell_fix<T, false>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y);
+      launch(k_sell_fix<T, false>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y, A->acc);
   }
 }
 
