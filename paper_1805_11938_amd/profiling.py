@@ -35,7 +35,7 @@ SCRUB = "k_scrub"
 COPY = "k_copy"
 # kernels that spmv_run launches (conversion, feature and selection kernels
 # run outside the scrubbed launches and are not counted)
-RUN_KERNELS = ("k_band_sum", "k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix",
+RUN_KERNELS = ("k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix",
                "k_c5_zero", "k_ell", "k_ell2", "k_ell_kc", "k_ell_kc4", "k_sell", "k_sell_kc", "k_sell_kc4", "k_sell_mixed", "k_sell_fix",
                "k_coo_tiles", "k_tile_fix", "k_csr_tiles", "k_csr_spmm", "k_csr_batched", "k_batch_tile_fix")
 
@@ -175,12 +175,12 @@ def launches(trace_csv: str, bench_json: str) -> str:
         idx = range(i * per, (i + 1) * per) if m else range(i, len(segs), n)
         spans = [(segs[j][-1][2] - segs[j][0][1]) / 1e3 for j in idx]
         us = sum(spans) / len(spans)
-        ks = []
+        ks = {}  # kernel -> launches of it in one run (one per column band)
         for k, _, _ in segs[idx[0]]:
-            if k not in ks:
-                ks.append(k)
+            ks[k] = ks.get(k, 0) + 1
+        names = ", ".join(k if c == 1 else f"{k} ×{c}" for k, c in ks.items())
         ev = bench["per_format"][lab]["ms"] * 1e3 if "per_format" in bench else math.nan
-        out.append(f"| {lab} | {', '.join(ks)} | {us:.2f} | {ev:.2f} | {alg / 1e6:.1f} | {alg / us / 1e3:.0f} |")
+        out.append(f"| {lab} | {names} | {us:.2f} | {ev:.2f} | {alg / 1e6:.1f} | {alg / us / 1e3:.0f} |")
     return "\n".join(out)
 
 
