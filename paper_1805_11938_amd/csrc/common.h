@@ -139,6 +139,7 @@ struct spmv_mat_s {
   int32_t* ct_trow = nullptr;
   int32_t* ct_info = nullptr;
   int64_t nseg = 0, nlong = 0; // CSR long rows cut into segments
+  int32_t maxlen = -1;         // CSR: the longest row (-1: not known)
   int2* segs = nullptr;        // (row, first nonzero) per segment
   int4* longs = nullptr;       // (row, first segment, segment count) per long row
   double* seg_part = nullptr;  // segment partial sums (run scratch)

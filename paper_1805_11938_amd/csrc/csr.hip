@@ -128,6 +128,9 @@ spmv_status_t csr_build_blocks(spmv_mat_s* A, hipStream_t s) {
   SPMV_TRY(build_partition(A, WU_ROWS, &A->nunits, &A->unit_row, s));
   const int64_t M = A->M;
   A->nseg = A->nlong = 0;
+  int32_t mx = 0;
+  SPMV_TRY(device_max_i32(A->ptr, M, 1, &mx, s));  // the longest row (0 when M = 0)
+  A->maxlen = mx;
   if (M == 0) return SPMV_OK;
   DTmp ns, il, sb, lp;
   SPMV_TRY(ns.alloc(sizeof(int32_t) * M));
@@ -749,132 +752,164 @@ spmv_status_t run_csr(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------- SpMM
-// Y = A X for k right-hand sides (row-major, k <= 64).  Same row blocks as
-// the SpMV kernel; the block's col/val are staged in LDS once and reused by
-// all k columns.  A lane owns VEC consecutive columns of one row: lanes
-// t / (k/VEC), ... take rows, so the k/VEC lanes of a row read its k values
-// of X per nonzero as k/VEC loads of VEC values (16 bytes when VEC > 1) and
-// write k consecutive values of Y.  VEC > 1 needs k, ldx and ldy multiples
-// of VEC and 16-byte aligned X and Y; otherwise VEC = 1.
-constexpr int SPMM_CAP = 2048;
+// Y = A X for k right-hand sides (row-major, k <= 64).  A workgroup takes a
+// block of rows; the block's col/val are staged in LDS once and reused by
+// all k columns.  A lane owns VEC consecutive columns of one row: the
+// k/VEC lanes of a row read its k values of X per nonzero as k/VEC loads of
+// VEC values (16 bytes when VEC > 1) and write k consecutive values of Y.
+// VEC > 1 needs k, ldx and ldy multiples of VEC and 16-byte aligned X and
+// Y; otherwise VEC = 1.
+//
+// Blocks: when every row is short enough (rb rows of the longest row fit
+// the LDS staging), blocks of rb = max(G, 64) rows, G = BS / (k/VEC) rows in
+// flight per workgroup, so every pass over the rows keeps all lanes busy;
+// otherwise the row blocks of the SpMV kernel (rows + nonzeros <= CSR_W).
+constexpr int SPMM_CAP = 2048;  // entries a block stages in LDS
+constexpr int SPMM_NB = 8;      // nonzeros of a row in flight per lane group
 
 template <typename T, int VEC>
 struct alignas(sizeof(T) * VEC) VecN {
   T v[VEC];
 };
 
+// Y is written once and not read again by the kernel: streaming stores keep
+// it from displacing gathered rows of X in the L2.
 template <typename T, int VEC>
-__global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __restrict__ blk_row,
-                                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                                 const T* __restrict__ val, const T* __restrict__ X, int64_t ldx,
-                                                 T* __restrict__ Y, int64_t ldy, int k) {
+__device__ __forceinline__ void spmm_store(T* p, const VecN<T, VEC>& o) {
+  if constexpr (VEC * sizeof(T) == 16) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 w;
+    __builtin_memcpy(&w, &o, 16);
+    __builtin_nontemporal_store(w, (f4*)p);
+  } else {
+    static_assert(VEC == 1, "16-byte lanes or single values");
+    __builtin_nontemporal_store(o.v[0], p);
+  }
+}
+
+template <typename T, int VEC>
+__global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __restrict__ blk_row, int rb,
+                                                 int64_t M, const int32_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                 const T* __restrict__ X, int64_t ldx, T* __restrict__ Y,
+                                                 int64_t ldy, int k) {
   typedef VecN<T, VEC> V;
-  __shared__ int32_t scol[SPMM_CAP];
-  __shared__ T sval[SPMM_CAP];
-  __shared__ double red[BS * VEC];
+  // staged entries; the long-row path's partial sums reuse the same bytes
+  static_assert(SPMM_CAP * (4 + sizeof(T)) >= BS * VEC * sizeof(double), "LDS reuse");
+  __shared__ __align__(16) char lds[SPMM_CAP * (4 + sizeof(T))];
+  int32_t* scol = (int32_t*)lds;
+  T* sval = (T*)(lds + SPMM_CAP * 4);
+  double* red = (double*)lds;
   const int t = threadIdx.x;
   const int kv = k / VEC;  // lanes per row
   const int G = BS / kv;
   const int g = t / kv, c = (t % kv) * VEC;
-  {  // one workgroup per row block, each XCD a contiguous range of blocks
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
-    if (b >= nblk) return;
-    const int64_t r0 = blk_row[b], r1 = blk_row[b + 1];
-    if (r0 >= r1) return;
-    const int64_t k0 = ptr[r0], E = ptr[r1] - k0;
-    if (E <= SPMM_CAP) {
-      if (E > 0) {  // all staging loads in flight (clamped, branch-free), then the LDS stores
-        int32_t cs[SPMM_CAP / BS];
-        T vs[SPMM_CAP / BS];
-        const uint32_t Em1 = (uint32_t)E - 1;
+  // one workgroup per row block, each XCD a contiguous range of blocks
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk) return;
+  const int64_t r0 = rb ? b * rb : blk_row[b];
+  const int64_t r1 = rb ? (r0 + rb < M ? r0 + rb : M) : blk_row[b + 1];
+  if (r0 >= r1) return;
+  const int64_t k0 = ptr[r0], E = ptr[r1] - k0;
+  if (E <= SPMM_CAP) {
+    if (E > 0) {  // all staging loads in flight (clamped, branch-free), then the LDS stores
+      int32_t cs[SPMM_CAP / BS];
+      T vs[SPMM_CAP / BS];
+      const uint32_t Em1 = (uint32_t)E - 1;
 #pragma unroll
-        for (int j = 0; j < SPMM_CAP / BS; ++j) {
-          const uint32_t q = (uint32_t)(t + j * BS), qq = q < (uint32_t)E ? q : Em1;
-          cs[j] = ldnt32(col + k0, qq);
-          vs[j] = ldnt32(val + k0, qq);
-        }
+      for (int j = 0; j < SPMM_CAP / BS; ++j) {
+        const uint32_t q = (uint32_t)(t + j * BS), qq = q < (uint32_t)E ? q : Em1;
+        cs[j] = ldnt32(col + k0, qq);
+        vs[j] = ldnt32(val + k0, qq);
+      }
 #pragma unroll
-        for (int j = 0; j < SPMM_CAP / BS; ++j) {
-          const int q = t + j * BS;
-          if (q < E) {
-            scol[q] = cs[j];
-            sval[q] = vs[j];
-          }
+      for (int j = 0; j < SPMM_CAP / BS; ++j) {
+        const int q = t + j * BS;
+        if (q < E) {
+          scol[q] = cs[j];
+          sval[q] = vs[j];
         }
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    if (g < G)
+      for (int64_t r = r0 + g; r < r1; r += G) {
+        const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
+        double s4[4][VEC];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) s4[i][v] = 0.0;
+        // SPMM_NB nonzeros at a time, all their gathers of X rows in flight;
+        // the last group repeats entry e-1 for its unused places and masks them
+        for (int q = a; q < e; q += SPMM_NB) {
+          const int n = e - q < SPMM_NB ? e - q : SPMM_NB;
+          int32_t cq[SPMM_NB];
+          T vq[SPMM_NB];
+          V xq[SPMM_NB];
+#pragma unroll
+          for (int u = 0; u < SPMM_NB; ++u) {
+            const int qq = q + (u < n ? u : n - 1);
+            cq[u] = scol[qq];
+            vq[u] = sval[qq];
+          }
+#pragma unroll
+          for (int u = 0; u < SPMM_NB; ++u) xq[u] = *(const V*)(X + (int64_t)cq[u] * ldx + c);
+#pragma unroll
+          for (int u = 0; u < SPMM_NB; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s4[u & 3][v] += u < n ? (double)vq[u] * (double)xq[u].v[v] : 0.0;
+        }
+        V out;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) out.v[v] = (T)((s4[0][v] + s4[1][v]) + (s4[2][v] + s4[3][v]));
+        spmm_store<T, VEC>(Y + r * ldy + c, out);
+      }
+  } else {
+    // rows one at a time: G groups stride over the row's nonzeros, then an
+    // ordered sum of the groups' partials in LDS
+    for (int64_t r = r0; r < r1; ++r) {
+      const int64_t a = ptr[r], e = ptr[r + 1];
+      double sv[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) sv[v] = 0.0;
       if (g < G)
-        for (int64_t r = r0 + g; r < r1; r += G) {
-          const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
-          double s4[4][VEC];
+        for (int64_t q = a + g; q < e; q += G) {
+          const double w = (double)ldnt(val + q);
+          const V xv = *(const V*)(X + (int64_t)ldnt(col + q) * ldx + c);
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) s4[i][v] = 0.0;
-          // 16 nonzeros at a time, all 16 gathers of X rows in flight; the
-          // last group repeats entry e-1 for its unused places and masks them
-          for (int q = a; q < e; q += 16) {
-            const int n = e - q < 16 ? e - q : 16;
-            int32_t cq[16];
-            T vq[16];
-            V xq[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-              const int qq = q + (u < n ? u : n - 1);
-              cq[u] = scol[qq];
-              vq[u] = sval[qq];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) xq[u] = *(const V*)(X + (int64_t)cq[u] * ldx + c);
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-#pragma unroll
-              for (int v = 0; v < VEC; ++v) s4[u & 3][v] += u < n ? (double)vq[u] * (double)xq[u].v[v] : 0.0;
-          }
-          V out;
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) out.v[v] = (T)((s4[0][v] + s4[1][v]) + (s4[2][v] + s4[3][v]));
-          *(V*)(Y + r * ldy + c) = out;
+          for (int v = 0; v < VEC; ++v) sv[v] += w * (double)xv.v[v];
         }
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) red[t * VEC + v] = sv[v];
       __syncthreads();
-    } else {
-      // rows one at a time: G groups stride over the row's nonzeros, then an
-      // ordered sum of the groups' partials in LDS
-      for (int64_t r = r0; r < r1; ++r) {
-        const int64_t a = ptr[r], e = ptr[r + 1];
-        double sv[VEC];
+      if (g == 0) {
+        V out;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) sv[v] = 0.0;
-        if (g < G)
-          for (int64_t q = a + g; q < e; q += G) {
-            const double w = (double)ldnt(val + q);
-            const V xv = *(const V*)(X + (int64_t)ldnt(col + q) * ldx + c);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) sv[v] += w * (double)xv.v[v];
-          }
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) red[t * VEC + v] = sv[v];
-        __syncthreads();
-        if (g == 0) {
-          V out;
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            double tot = 0.0;
-            for (int gg = 0; gg < G; ++gg) tot += red[(gg * kv + t % kv) * VEC + v];
-            out.v[v] = (T)tot;
-          }
-          *(V*)(Y + r * ldy + c) = out;
+        for (int v = 0; v < VEC; ++v) {
+          double tot = 0.0;
+          for (int gg = 0; gg < G; ++gg) tot += red[(gg * kv + t % kv) * VEC + v];
+          out.v[v] = (T)tot;
         }
-        __syncthreads();
+        spmm_store<T, VEC>(Y + r * ldy + c, out);
       }
+      __syncthreads();
     }
   }
 }
 
 template <typename T, int VEC>
 static void launch_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {
-  launch(k_csr_spmm<T, VEC>, (unsigned)A->nblk, BS, s, A->nblk, A->blk_row, A->ptr, A->col, (const T*)A->val,
-         (const T*)X, ldx, (T*)Y, ldy, k);  // one workgroup per row block
+  const int64_t G = BS / (k / VEC);
+  const int64_t rb = std::max<int64_t>(G, 64);
+  if (A->maxlen >= 0 && rb * std::max<int64_t>(A->maxlen, 1) <= SPMM_CAP) {
+    const int64_t nb = cdiv(A->M, rb);  // blocks of rb rows
+    launch(k_csr_spmm<T, VEC>, (unsigned)nb, BS, s, nb, (const int32_t*)nullptr, (int)rb, A->M, A->ptr, A->col,
+           (const T*)A->val, (const T*)X, ldx, (T*)Y, ldy, k);
+  } else {  // the SpMV kernel's row blocks
+    launch(k_csr_spmm<T, VEC>, (unsigned)A->nblk, BS, s, A->nblk, (const int32_t*)A->blk_row, 0, A->M, A->ptr,
+           A->col, (const T*)A->val, (const T*)X, ldx, (T*)Y, ldy, k);
+  }
 }
 
 spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {

@@ -163,7 +163,7 @@ spmv_status_t device_max_i32(const int32_t* a, int64_t n, int lens_from_ptr, int
   DTmp d;
   SPMV_TRY(d.alloc(sizeof(int32_t)));
   SPMV_HIP(hipMemsetAsync(d.p, 0, sizeof(int32_t), s));
-  k_max_i32<<<grid_for(n, BS, 4096), BS, 0, s>>>(a, n, lens_from_ptr, d.as<int32_t>());
+  k_max_i32<<<grid_for(n, BS, 1024), BS, 0, s>>>(a, n, lens_from_ptr, d.as<int32_t>());
   SPMV_LAUNCH_CHECK();
   return copy_to_host(out_host, d.p, sizeof(int32_t), s);
 }
