@@ -117,8 +117,15 @@ const char* spmv_last_error(void);
 /* Device bytes the library currently holds: live handles, batches, models and
  * the workspaces it keeps (not the caller's buffers).  With the environment
  * variable SPMV_MEM_CAP_BYTES set (read once per process), an allocation that
- * would take this above the cap fails with SPMV_ERR_OOM. */
+ * would take this above the cap fails with SPMV_ERR_OOM.
+ * Arrays the library frees (a destroyed handle, a conversion's temporaries)
+ * are kept for its later allocations on the same device, up to
+ * SPMV_CACHE_BYTES (read once per process; default 16 GiB, 0 keeps none);
+ * kept blocks are not counted here. */
 int64_t spmv_mem_in_use(void);
+/* Hands every kept free block back to HIP (hipFree); returns the bytes
+ * released.  Safe at any time: handles and their arrays are not affected. */
+int64_t spmv_mem_release(void);
 
 /* ------------------------------------------------------------ creation */
 

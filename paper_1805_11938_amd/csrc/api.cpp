@@ -141,6 +141,7 @@ const char* spmv_status_str(spmv_status_t st) {
 const char* spmv_last_error(void) { return last_error_cstr(); }
 
 int64_t spmv_mem_in_use(void) { return mem_in_use(); }
+int64_t spmv_mem_release(void) { return mem_release(); }
 
 spmv_status_t spmv_mat_from_csr(int64_t M, int64_t N, int64_t nnz, const int32_t* ptr, const int32_t* col,
                                 const void* val, spmv_dtype_t dt, int src_on_device, uint32_t flags, spmv_stream_t s,

@@ -43,7 +43,8 @@ spmv_status_t fail(spmv_status_t st, const char* fmt, ...);
 // the library's live device memory (OOM is then reported, never a fault).
 spmv_status_t dmalloc(void** p, size_t bytes);
 void dfree(void* p);
-int64_t mem_in_use();  // bytes the library holds from dmalloc
+int64_t mem_in_use();  // bytes the library holds from dmalloc (kept free blocks not counted)
+int64_t mem_release(); // hands every kept free block back to HIP; returns the bytes released
 
 // A scoped device buffer for temporaries inside conversions.  Its release
 // waits for the device first, so no queued kernel can still be using it.

@@ -2,7 +2,9 @@
 // stable LSD radix sort of (key, value) pairs, reductions and fills.
 #include <cstdarg>
 #include <cstdlib>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "common.h"
 
@@ -34,14 +36,38 @@ spmv_status_t fail(spmv_status_t st, const char* fmt, ...) {
 const char* last_error_cstr() { return g_err.c_str(); }
 
 // --------------------------------------------------------------- memory
+// Device arrays come from hipMalloc, and freed ones are kept for reuse per
+// device: hipMalloc and hipFree each cost tens of microseconds and hipFree
+// waits for the device, while a format conversion allocates and frees a
+// dozen arrays.  A request takes the smallest kept block of its device that
+// holds it and wastes at most a quarter of it; blocks are rounded up to
+// 256 B below 1 MiB and to 2 MiB above.  At most SPMV_CACHE_BYTES (read
+// once; default 16 GiB, 0 keeps nothing) are kept, largest released first;
+// a failed hipMalloc releases every kept block of the device and tries once
+// more.  dfree waits for the device before keeping a block, as hipFree
+// would, so no kernel still reads it when it is handed out again.
 static std::mutex g_mem_mu;
-static int64_t g_live = 0;
-static std::vector<std::pair<void*, size_t>> g_sizes;
+static int64_t g_live = 0;    // bytes handed out (as requested)
+static int64_t g_cached = 0;  // bytes of kept free blocks
+struct LiveBlock {
+  size_t req, cap;
+  int dev;
+};
+static std::unordered_map<void*, LiveBlock> g_blocks;
+static std::multimap<std::pair<int, size_t>, void*> g_free;  // (device, block bytes) -> block
 
 static int64_t mem_cap() {
   static int64_t cap = [] {
     const char* e = getenv("SPMV_MEM_CAP_BYTES");
     return e ? (int64_t)strtoll(e, nullptr, 10) : (int64_t)0;
+  }();
+  return cap;
+}
+
+static int64_t cache_cap() {
+  static int64_t cap = [] {
+    const char* e = getenv("SPMV_CACHE_BYTES");
+    return e ? (int64_t)strtoll(e, nullptr, 10) : (int64_t)16 << 30;
   }();
   return cap;
 }
@@ -54,46 +80,93 @@ int64_t default_max_bytes() {
   return v;
 }
 
+static size_t block_bytes(size_t b) {
+  if (b <= ((size_t)1 << 20)) return (b + 255) / 256 * 256;
+  const size_t m = (size_t)2 << 20;
+  return (b + m - 1) / m * m;
+}
+
+// releases kept blocks of device dev (all devices when dev < 0) until at
+// most keep bytes stay kept; largest first.  Caller holds g_mem_mu.
+static int64_t release_locked(int dev, int64_t keep) {
+  int64_t freed = 0;
+  for (auto it = g_free.end(); it != g_free.begin() && g_cached > keep;) {
+    --it;
+    if (dev >= 0 && it->first.first != dev) continue;
+    (void)hipFree(it->second);
+    g_cached -= (int64_t)it->first.second;
+    freed += (int64_t)it->first.second;
+    it = g_free.erase(it);
+  }
+  return freed;
+}
+
 spmv_status_t dmalloc(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;  // never hand out null for an empty array
-  {
-    std::lock_guard<std::mutex> g(g_mem_mu);
-    int64_t cap = mem_cap();
-    if (cap > 0 && g_live + (int64_t)bytes > cap)
-      return fail(SPMV_ERR_OOM, "SPMV_MEM_CAP_BYTES=%lld exceeded (live %lld + %zu)", (long long)cap,
-                  (long long)g_live, bytes);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t want = block_bytes(bytes);
+  std::lock_guard<std::mutex> g(g_mem_mu);
+  const int64_t cap = mem_cap();
+  if (cap > 0 && g_live + (int64_t)bytes > cap)
+    return fail(SPMV_ERR_OOM, "SPMV_MEM_CAP_BYTES=%lld exceeded (live %lld + %zu)", (long long)cap,
+                (long long)g_live, bytes);
+  auto it = g_free.lower_bound(std::make_pair(dev, want));
+  if (it != g_free.end() && it->first.first == dev && it->first.second <= want + want / 4) {
+    *p = it->second;
+    g_cached -= (int64_t)it->first.second;
+    g_blocks[*p] = LiveBlock{bytes, it->first.second, dev};
+    g_free.erase(it);
+    g_live += (int64_t)bytes;
+    return SPMV_OK;
   }
-  hipError_t e = hipMalloc(p, bytes);
+  hipError_t e = hipMalloc(p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_locked(dev, 0);
+    e = hipMalloc(p, want);
+  }
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
-    return fail(SPMV_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return fail(SPMV_ERR_OOM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
   }
-  std::lock_guard<std::mutex> g(g_mem_mu);
+  g_blocks[*p] = LiveBlock{bytes, want, dev};
   g_live += (int64_t)bytes;
-  g_sizes.emplace_back(*p, bytes);
   return SPMV_OK;
 }
 
 void dfree(void* p) {
   if (!p) return;
-  {
-    std::lock_guard<std::mutex> g(g_mem_mu);
-    for (size_t i = 0; i < g_sizes.size(); ++i)
-      if (g_sizes[i].first == p) {
-        g_live -= (int64_t)g_sizes[i].second;
-        g_sizes[i] = g_sizes.back();
-        g_sizes.pop_back();
-        break;
-      }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(g_mem_mu);
+  auto it = g_blocks.find(p);
+  if (it == g_blocks.end()) return;  // not ours
+  const LiveBlock b = it->second;
+  g_blocks.erase(it);
+  g_live -= (int64_t)b.req;
+  if (cache_cap() <= 0 || (int64_t)b.cap > cache_cap()) {
+    (void)hipFree(p);
+    return;
   }
-  (void)hipFree(p);
+  if (b.dev != dev) (void)hipSetDevice(b.dev);
+  (void)hipDeviceSynchronize();  // the block's last use has finished
+  if (b.dev != dev) (void)hipSetDevice(dev);
+  g_free.emplace(std::make_pair(b.dev, b.cap), p);
+  g_cached += (int64_t)b.cap;
+  if (g_cached > cache_cap()) release_locked(-1, cache_cap());
 }
 
 int64_t mem_in_use() {
   std::lock_guard<std::mutex> g(g_mem_mu);
   return g_live;
+}
+
+int64_t mem_release() {
+  std::lock_guard<std::mutex> g(g_mem_mu);
+  return release_locked(-1, 0);
 }
 
 int64_t resident_blocks(int per_cu) {

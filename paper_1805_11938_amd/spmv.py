@@ -63,7 +63,8 @@ EXPORTED = [
     "spmv_autotune", "spmv_features", "spmv_model_create", "spmv_model_load", "spmv_model_save",
     "spmv_model_params", "spmv_model_free", "spmv_select", "spmv_mlp_forward", "spmv_mlp_backward", "spmv_mlp_adam",
     "spmv_scale_features", "spmv_feature_range", "spmv_mlp_train", "spmv_run_timed", "spmv_spmm_timed",
-    "spmv_batch_run_timed", "spmv_autotune_cache_clear", "spmv_mem_in_use", "spmv_mlp_backward_noalloc",
+    "spmv_batch_run_timed", "spmv_autotune_cache_clear", "spmv_mem_in_use", "spmv_mem_release",
+    "spmv_mlp_backward_noalloc",
 ]
 
 _L = None
@@ -123,6 +124,7 @@ def lib():
             "spmv_batch_run_timed": (st, [vp, vp, vp, vp, vp, vp]),
             "spmv_autotune_cache_clear": (None, []),
             "spmv_mem_in_use": (i64, []),
+            "spmv_mem_release": (i64, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

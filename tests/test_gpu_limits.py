@@ -4,6 +4,8 @@
   fix-up passes add in a fixed order, never by atomics);
 * SPMV_MEM_CAP_BYTES turns an allocation over the cap into SPMV_ERR_OOM and
   the failed conversion leaves no device memory behind;
+* freed arrays are kept and handed out again (a second conversion reuses
+  them, with identical results) and spmv_mem_release returns them to HIP;
 * the autotuner's cache keeps callers with different flags apart;
 * the selector falls back to exhaustive profiling when the network predicts a
   format that cannot hold the matrix (ELL over the byte cap).
@@ -103,6 +105,28 @@ def test_memory_cap_gives_oom_without_leak(torch):
     assert out["after"] == out["before"]             # the failed conversion freed all it took
     assert out["before"] < out["mid"] <= cap         # the CSR5 handle fits under the cap
     assert out["end"] == out["before"]               # and is returned on free
+
+
+def test_freed_blocks_are_reused_and_released(torch):
+    A = synth.stencil27(14, 2)
+    H = S.Matrix.from_host(A)
+    L = S.lib()
+    x = torch.from_numpy(synth.vector(A.N, 4)).cuda()
+    before = L.spmv_mem_in_use()
+    outs = []
+    for rep in range(3):
+        B = H.convert("csr5", csr5_sigma=16)
+        assert L.spmv_mem_in_use() > before
+        outs.append(B.run(x).cpu().numpy())
+        del B
+        assert L.spmv_mem_in_use() == before         # kept blocks are not counted as held
+        if rep == 1:
+            assert L.spmv_mem_release() > 0          # the freed CSR5 arrays were kept
+            assert L.spmv_mem_release() == 0         # and are all gone now
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
+    yref, den = reference(A, synth.vector(A.N, 4), 0)
+    assert rowwise_err(outs[0], yref, den) <= TOL[0]
 
 
 def test_autotune_cache_keeps_flags_apart(torch):
