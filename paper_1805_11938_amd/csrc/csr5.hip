@@ -134,11 +134,6 @@ __global__ void k_c5_erows(int64_t M, const int32_t* ptr, const int32_t* rank, i
 }
 
 // y = 0 on the empty rows (the tiles write only rows that own entries)
-template <typename T>
-__global__ void k_c5_zero(int64_t n, const int32_t* __restrict__ erows, T* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[erows[i]] = (T)0;
-}
 
 __global__ void k_c5_nzbase(int64_t T, const int32_t* tile_ptr, const int32_t* rank, int32_t* base) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (int64_t)gridDim.x * blockDim.x)
@@ -316,6 +311,8 @@ struct C5Args {
   const int32_t* nzbase;
   int32_t tail_rlo, tail_row;
   double* carry;
+  const int32_t* erows;  // the empty rows (written 0 unless adding)
+  int64_t nerows;
   int add;  // add the rows' sums onto y (a column band after the first)
 };
 
@@ -330,7 +327,7 @@ __device__ __forceinline__ void c5_write(const C5Args& a, int64_t t, int64_t row
     put_y(y, row0 + j, s, a.add);
     return;
   }
-  put_y(y, a.nzrow[nzb + j], s, a.add);  // empty rows are zeroed by k_c5_zero (left alone when adding)
+  put_y(y, a.nzrow[nzb + j], s, a.add);  // empty rows are zeroed by k_csr5 (left alone when adding)
 }
 
 // The tail (entries past the last full tile) in CSR order.  Its leading
@@ -449,6 +446,9 @@ __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val
   const int64_t step = (int64_t)gridDim.x * tpb;
   const int64_t first = W64 ? (int64_t)blockIdx.x * tpb + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE)
                             : (int64_t)blockIdx.x * tpb + threadIdx.x / omega;
+  if (EMPTY && !a.add)  // no tile writes an empty row: zero them beside the tiles
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.nerows; i += (int64_t)gridDim.x * BS)
+      y[a.erows[i]] = (T)0;
   for (int64_t t = first; t < a.ntiles; t += step) c5_tile<T, SIG, EMPTY, W64>(a, t, l, val, x, y);
   c5_tail<T>(a, val, x, y);
 }
@@ -503,14 +503,12 @@ static spmv_status_t run_csr5_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) 
   a.tail_rlo = A->tail_rlo;
   a.tail_row = A->c5_tail_row;
   a.carry = A->carry;
+  a.erows = A->erows;
+  a.nerows = A->nerows;
   a.add = A->acc;
   // one workgroup per BS / omega tiles: the dispatcher balances them (a
   // persistent grid of 8 workgroups per CU was 4% slower on the stencil)
   const unsigned grid = (unsigned)std::max<int64_t>(1, a.nb_main);
-  if (A->nerows > 0 && !A->acc) {
-    launch(k_c5_zero<T>, (unsigned)std::min<int64_t>(cdiv(A->nerows, BS), 4096), BS, s, A->nerows, A->erows, y);
-    SPMV_LAUNCH_CHECK();
-  }
   if (A->has_empty) launch_c5<T, true>(a, grid, (const T*)A->val, x, y, s);
   else launch_c5<T, false>(a, grid, (const T*)A->val, x, y, s);
   SPMV_LAUNCH_CHECK();

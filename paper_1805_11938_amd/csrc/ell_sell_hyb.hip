@@ -655,33 +655,41 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
   if (r >= 0) put_y(y, r, (sa[0] + sa[1]) + (sa[2] + sa[3]), add);
 }
 
-// one thread per (wide chunk, stored row): y = sum of the slices' partials in order
+// One workgroup per wide chunk, BS / C threads per stored row: thread j of
+// row p sums slices j, j + BS/C, ... (eight loads in flight, eight running
+// sums), then thread 0 of the row adds the rows' BS/C sums in order and
+// writes y.  The longest chunks (tens of slices on Zipf rows) then take a
+// few rounds of loads instead of one per eight slices.
 template <typename T, bool PERM>
-__global__ void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restrict__ wide,
-                           const int32_t* __restrict__ perm, const double* __restrict__ part, T* __restrict__ y,
-                           int add) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wi = gid / C;
+__global__ __launch_bounds__(BS) void k_sell_fix(int64_t M, int64_t nwide, int C, const int4* __restrict__ wide,
+                                                 const int32_t* __restrict__ perm, const double* __restrict__ part,
+                                                 T* __restrict__ y, int add) {
+  __shared__ double red[BS];
+  const int64_t wi = blockIdx.x;
   if (wi >= nwide) return;
-  const int p = (int)(gid % C);
+  const int t = threadIdx.x, S = BS / C, p = t % C, j = t / C;
   const int4 wd = wide[wi];  // chunk, first item, item count
-  // eight running sums (slice i goes to sum i mod 8) keep eight loads in
-  // flight on the longest chunks; they are combined in a fixed order
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double* q = part + (int64_t)wd.y * C + p;
-  int i = 0;
-  for (; i + 8 <= wd.z; i += 8) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = j; i < wd.z; i += 8 * S) {
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = q[(int64_t)(i + u) * C];
+    for (int u = 0; u < 8; ++u) {
+      const int k = i + u * S;
+      v[u] = k < wd.z ? q[(int64_t)k * C] : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
-  for (int u = 0; i < wd.z; ++i, ++u) a[u] += q[(int64_t)i * C];
-  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  const int64_t pos = (int64_t)wd.x * C + p;
-  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-  if (r >= 0) put_y(y, r, s, add);
+  red[t] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  __syncthreads();
+  if (j == 0) {
+    double sum = red[p];
+    for (int jj = 1; jj < S; ++jj) sum += red[jj * C + p];
+    const int64_t pos = (int64_t)wd.x * C + p;
+    const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+    if (r >= 0) put_y(y, r, sum, add);
+  }
 }
 
 template <typename T, int LOGC, int KC>
@@ -775,7 +783,7 @@ static void launch_sell_c(spmv_mat_s* A, const void* x, void* y, hipStream_t s) 
   }
   if (A->kc_first == 0) return;
   if (A->nwide > 0) {
-    const unsigned gf = (unsigned)cdiv(A->nwide << LOGC, BS);
+    const unsigned gf = (unsigned)A->nwide;  // one workgroup per wide chunk
     if (A->perm)
       launch(k_sell_fix<T, true>, gf, BS, s, A->M, A->nwide, 1 << LOGC, A->wide, A->perm, A->part, (T*)y, A->acc);
     else
