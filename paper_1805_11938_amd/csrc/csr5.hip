@@ -353,8 +353,10 @@ __device__ void c5_tail(const C5Args& a, const T* __restrict__ val, const T* __r
   }
 }
 
-// One tile (omega lanes).  t and row0 are wave-uniform when W64.
-template <typename T, int SIG, bool EMPTY, bool W64>
+// One tile (omega lanes).  t and row0 are wave-uniform when W64.  PY: the
+// tile adds onto y with the old values of each lane's first rows loaded
+// beside its streams (see below).
+template <typename T, int SIG, bool EMPTY, bool W64, bool PY = false>
 __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const T* __restrict__ val,
                                         const T* __restrict__ x, T* __restrict__ y) {
   const int omega = W64 ? WAVE : a.omega;
@@ -378,6 +380,31 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
   double acc = 0.0, head = 0.0;
   bool seen = false;
   int lf = 0;
+  // Adding onto y (PY, a column band after the first): the lane writes rows
+  // yoff, yoff + 1, ... in that order, so their old values (and, with empty
+  // rows, their row numbers) for the first C5_PY of them are loaded beside
+  // the tile's streams instead of one dependent load per row written
+  // (zipf_1M, sigma = 16 over two bands: 169.5 -> 165 us).
+  constexpr int C5_PY = 4;
+  double yp[C5_PY] = {0.0, 0.0, 0.0, 0.0};
+  int32_t rp[C5_PY] = {0, 0, 0, 0};
+  int nw = 0;  // rows (or the carry) written so far
+  auto put = [&](int j, double sum) {
+    if (PY && nw < C5_PY && !(j == 0 && cont)) {
+      const int64_t r = EMPTY ? (int64_t)rp[0] : row0 + j;
+      y[r] = (T)(yp[0] + sum);
+    } else {
+      c5_write<T, EMPTY>(a, t, row0, nzb, cont, j, sum, y);
+    }
+    if (PY) {
+#pragma unroll
+      for (int u = 0; u + 1 < C5_PY; ++u) {
+        yp[u] = yp[u + 1];
+        rp[u] = rp[u + 1];
+      }
+      ++nw;
+    }
+  };
   if (SIG > 0) {
     int32_t c[SIG > 0 ? SIG : 1];
     T v[SIG > 0 ? SIG : 1], xv[SIG > 0 ? SIG : 1];
@@ -388,6 +415,16 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
       c[i] = ldnt32(cb, (uint32_t)(i * omega + l));
       v[i] = ldnt32(vb, (uint32_t)(i * omega + l));
     }
+    if (PY) {
+      if (EMPTY) {
+#pragma unroll
+        for (int u = 0; u < C5_PY; ++u)
+          if (u < pc) rp[u] = a.nzrow[nzb + yoff + u];
+      }
+#pragma unroll
+      for (int u = 0; u < C5_PY; ++u)
+        if (u < pc && !(yoff + u == 0 && cont)) yp[u] = (double)y[EMPTY ? (int64_t)rp[u] : row0 + yoff + u];
+    }
     issue_fence();
 #pragma unroll
     for (int i = 0; i < SIG; ++i) xv[i] = ld32(x, (uint32_t)c[i]);
@@ -395,7 +432,7 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
 #pragma unroll
     for (int i = 0; i < SIG; ++i) {
       if ((F >> i) & 1u) {
-        if (seen) c5_write<T, EMPTY>(a, t, row0, nzb, cont, yoff + lf - 1, acc, y);
+        if (seen) put(yoff + lf - 1, acc);
         else head = acc;
         seen = true;
         acc = 0.0;
@@ -432,12 +469,12 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
   }
   double S = __shfl_down(Rv, 1, omega);
   if (l == omega - 1) S = 0.0;
-  if (seen) c5_write<T, EMPTY>(a, t, row0, nzb, cont, yoff + lf - 1, acc + S, y);
+  if (seen) put(yoff + lf - 1, acc + S);
 }
 
 // Each lane group takes its tile (the loop covers grids smaller than the
 // tile count); then the grid sums the CSR-ordered tail.
-template <typename T, int SIG, bool EMPTY, bool W64>
+template <typename T, int SIG, bool EMPTY, bool W64, bool PY = false>
 __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val, const T* __restrict__ x,
                                              T* __restrict__ y) {
   const int omega = W64 ? WAVE : a.omega;
@@ -449,7 +486,7 @@ __global__ __launch_bounds__(BS) void k_csr5(C5Args a, const T* __restrict__ val
   if (EMPTY && !a.add)  // no tile writes an empty row: zero them beside the tiles
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.nerows; i += (int64_t)gridDim.x * BS)
       y[a.erows[i]] = (T)0;
-  for (int64_t t = first; t < a.ntiles; t += step) c5_tile<T, SIG, EMPTY, W64>(a, t, l, val, x, y);
+  for (int64_t t = first; t < a.ntiles; t += step) c5_tile<T, SIG, EMPTY, W64, PY>(a, t, l, val, x, y);
   c5_tail<T>(a, val, x, y);
 }
 
@@ -465,20 +502,23 @@ __global__ __launch_bounds__(BS) void k_csr5_fix(int64_t nchains, const int32_t*
   if (__lane_id() == 0) y[row] = (T)((double)y[row] + s);
 }
 
-template <typename T, bool EMPTY, bool W64>
+template <typename T, bool EMPTY, bool W64, bool PY = false>
 static void launch_c5w(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
   switch (a.sigma) {
-    case 4: launch(k_csr5<T, 4, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
-    case 8: launch(k_csr5<T, 8, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
-    case 16: launch(k_csr5<T, 16, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
-    case 32: launch(k_csr5<T, 32, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
-    default: launch(k_csr5<T, 0, EMPTY, W64>, grid, BS, s, a, val, x, y); break;
+    case 4: launch(k_csr5<T, 4, EMPTY, W64, PY>, grid, BS, s, a, val, x, y); break;
+    case 8: launch(k_csr5<T, 8, EMPTY, W64, PY>, grid, BS, s, a, val, x, y); break;
+    case 16: launch(k_csr5<T, 16, EMPTY, W64, PY>, grid, BS, s, a, val, x, y); break;
+    case 32: launch(k_csr5<T, 32, EMPTY, W64, PY>, grid, BS, s, a, val, x, y); break;
+    default: launch(k_csr5<T, 0, EMPTY, W64, PY>, grid, BS, s, a, val, x, y); break;
   }
 }
 
 template <typename T, bool EMPTY>
 static void launch_c5(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
-  if (a.omega == WAVE) launch_c5w<T, EMPTY, true>(a, grid, val, x, y, s);
+  // adding onto y: the old values prefetched (sigma <= 16; with sigma = 32
+  // the extra registers cost more than the dependent loads they save)
+  if (a.omega == WAVE && a.add && a.sigma <= 16) launch_c5w<T, EMPTY, true, true>(a, grid, val, x, y, s);
+  else if (a.omega == WAVE) launch_c5w<T, EMPTY, true>(a, grid, val, x, y, s);
   else launch_c5w<T, EMPTY, false>(a, grid, val, x, y, s);
 }
 

@@ -53,6 +53,7 @@ FORMAT_CONFIGS = [
     ("csr5", {"csr5_omega": 16, "csr5_sigma": 3}),
     ("csr5", {"bands": 3}),
     ("csr5", {"csr5_sigma": 4, "bands": 8}),
+    ("csr5", {"csr5_sigma": 32, "bands": 2}),
     ("ell", {}),
     ("ell", {"flags": 4}),
     ("ell", {"flags": 64}),
