@@ -765,7 +765,7 @@ spmv_status_t run_csr(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
 // flight per workgroup, so every pass over the rows keeps all lanes busy;
 // otherwise the row blocks of the SpMV kernel (rows + nonzeros <= CSR_W).
 constexpr int SPMM_CAP = 2048;  // entries a block stages in LDS
-constexpr int SPMM_NB = 8;      // nonzeros of a row in flight per lane group
+constexpr int SPMM_NB = 6;      // nonzeros of a row in flight per lane group
 
 template <typename T, int VEC>
 struct alignas(sizeof(T) * VEC) VecN {
@@ -835,11 +835,11 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
     if (g < G)
       for (int64_t r = r0 + g; r < r1; r += G) {
         const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
-        double s4[4][VEC];
+        double s2[2][VEC];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) s4[i][v] = 0.0;
+          for (int v = 0; v < VEC; ++v) s2[i][v] = 0.0;
         // SPMM_NB nonzeros at a time, all their gathers of X rows in flight;
         // the last group repeats entry e-1 for its unused places and masks them
         for (int q = a; q < e; q += SPMM_NB) {
@@ -858,11 +858,11 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
 #pragma unroll
           for (int u = 0; u < SPMM_NB; ++u)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) s4[u & 3][v] += u < n ? (double)vq[u] * (double)xq[u].v[v] : 0.0;
+            for (int v = 0; v < VEC; ++v) s2[u & 1][v] += u < n ? (double)vq[u] * (double)xq[u].v[v] : 0.0;
         }
         V out;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) out.v[v] = (T)((s4[0][v] + s4[1][v]) + (s4[2][v] + s4[3][v]));
+        for (int v = 0; v < VEC; ++v) out.v[v] = (T)(s2[0][v] + s2[1][v]);
         spmm_store<T, VEC>(Y + r * ldy + c, out);
       }
   } else {
