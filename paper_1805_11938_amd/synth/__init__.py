@@ -187,6 +187,15 @@ def uniform_random(M: int, N: int, mean: float, seed: int, val_seed: int) -> Hos
     return HostCSR(M, N, ptr, col, normal(len(col), val_seed), name=f"uniform_{M}", meta=dict(mean=mean))
 
 
+def from_lengths(M: int, N: int, lens, seed: int, val_seed: int) -> HostCSR:
+    """Rows of the given lengths (each <= N) with distinct uniformly random
+    columns, sorted, and standard-normal values."""
+    lens = np.ascontiguousarray(lens, np.int32)
+    assert lens.shape == (M,) and (lens >= 0).all() and (lens <= N).all()
+    ptr, col = _random_cols(M, N, lens, seed)
+    return HostCSR(M, N, ptr, col, normal(len(col), val_seed), name=f"lengths_{M}")
+
+
 def uniform_len_random(M: int, N: int, lo: int, hi: int, seed: int, val_seed: int) -> HostCSR:
     lens = np.empty(M, np.int32)
     _lib().syn_lens_uniform_int(M, N, int(lo), int(hi), int(seed), _p(lens))

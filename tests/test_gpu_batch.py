@@ -71,6 +71,42 @@ def test_spmm_wide_lanes(torch, dt, k, ldx, ldy):
             assert rowwise_err(Y[:, c], Yref[:, c], den) <= TOL[dt], (name, dt, k, c)
 
 
+def _spmm_block_case(kind):
+    """Row-length patterns around the SpMM block rule: blocks of max(G, 64)
+    rows are taken when that many rows of the longest row fit the 2,048
+    staged entries (k = 8 and 16 in FP64: 64 rows, so rows of up to 32;
+    k = 4: 128 rows of up to 16), else the SpMV row blocks.  M = 1,000
+    leaves a ragged last block."""
+    M, N = 1000, 3000
+    rng = np.random.default_rng(7)
+    lens = rng.integers(0, 20, M).astype(np.int32)
+    if kind == "max32":          # the rule's limit: 64 x 32 = 2,048 entries
+        lens[rng.choice(M, 40, replace=False)] = 32
+        lens[64:128] = 32        # one whole block at the limit
+    elif kind == "max33":        # one row past it: the SpMV row blocks
+        lens[rng.choice(M, 40, replace=False)] = 32
+        lens[500] = 33
+    elif kind == "max16":        # k = 4 (128-row blocks) at its limit: 128 x 16
+        lens = rng.integers(0, 17, M).astype(np.int32)
+        lens[128:256] = 16
+    elif kind == "empty_blocks":  # whole blocks without entries, then entries
+        lens[:256] = 0
+        lens[900:] = 0
+    return synth.from_lengths(M, N, lens, 11, 12)
+
+
+@pytest.mark.parametrize("k", [4, 8, 16])
+@pytest.mark.parametrize("kind", ["max32", "max33", "max16", "empty_blocks"])
+def test_spmm_block_rule_edges(torch, kind, k):
+    A = _spmm_block_case(kind)
+    X = synth.uniform(A.N * k, 40 + k, -1.0, 1.0).reshape(A.N, k)
+    Yref = oracle.csr_spmm(A.M, A.ptr, A.col, A.val, X)
+    Y = S.Matrix.from_host(A).spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(k):
+        den = oracle.csr_absspmv(A.M, A.ptr, A.col, A.val, X[:, c])
+        assert rowwise_err(Y[:, c], Yref[:, c], den) <= TOL[0], (kind, k, c)
+
+
 def test_spmm_integer_exact(torch):
     A = synth.random_pattern(900, 700, 0.02, 7, integer_values=True)
     X = np.round(synth.uniform(700 * 8, 3, -8, 8)).reshape(700, 8)
