@@ -101,6 +101,9 @@ typedef struct {
 #define SPMV_FLAG_SPLIT4 64u    /* ELL with K <= 32 and SELL chunks of C = 64 at most 32 wide: four waves share
                                   each 64 rows, each taking a quarter of every row's slots; the four sums are
                                   added in wave order (fewer registers per wave, more loads in flight per CU) */
+#define SPMV_FLAG_SPLIT6 128u   /* SELL chunks of C = 64 at most 32 wide: six waves share each chunk, each taking
+                                  a sixth of every row's slots, sums added in wave order (over SPLIT4 when both
+                                  are set; other formats and chunk heights ignore it) */
 
 typedef struct {
   int32_t fmt, dtype;

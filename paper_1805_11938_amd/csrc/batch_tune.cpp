@@ -236,16 +236,17 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
             p.sell_C = C;
             p.sell_sigma = (int32_t)sg;
             p.bands = 1;
-            p.flags &= ~SPMV_FLAG_SPLIT4;
+            p.flags &= ~(SPMV_FLAG_SPLIT4 | SPMV_FLAG_SPLIT6);
           });
-          // C = 64: also four waves per chunk
+          // C = 64: also four and six waves per chunk
           if (C == 64)
-            add([C, sg](spmv_params_t& p) {
-              p.sell_C = C;
-              p.sell_sigma = (int32_t)sg;
-              p.bands = 1;
-              p.flags |= SPMV_FLAG_SPLIT4;
-            });
+            for (uint32_t sp : {(uint32_t)SPMV_FLAG_SPLIT4, (uint32_t)SPMV_FLAG_SPLIT6})
+              add([C, sg, sp](spmv_params_t& p) {
+                p.sell_C = C;
+                p.sell_sigma = (int32_t)sg;
+                p.bands = 1;
+                p.flags = (p.flags & ~(SPMV_FLAG_SPLIT4 | SPMV_FLAG_SPLIT6)) | sp;
+              });
         }
       }
       if (!xbands.empty()) {
@@ -256,7 +257,7 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
               p.sell_C = C;
               p.sell_sigma = all;
               p.bands = nb;
-              p.flags &= ~SPMV_FLAG_SPLIT4;
+              p.flags &= ~(SPMV_FLAG_SPLIT4 | SPMV_FLAG_SPLIT6);
             });
       }
       break;

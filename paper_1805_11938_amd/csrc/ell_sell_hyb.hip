@@ -544,27 +544,30 @@ __global__ __launch_bounds__(WAVE) void k_sell_kc(int64_t M, int64_t c0, int64_t
   if (r >= 0) put_y(y, r, (sa[0] + sa[1]) + (sa[2] + sa[3]), add);
 }
 
-// Narrow SELL with C = 64, four waves per chunk: wave h takes the slots
-// [h*q, min(w, (h+1)*q)) of each stored row, q = ceil(w/4), with every one of
-// its loads in flight; the four sums are added in wave order through LDS.
-// Against one wave per chunk this holds a quarter of the registers per wave
-// (twice the waves per SIMD) and a quarter of the dependent round trip per
-// wave, so the chunk streams keep more bytes in flight.
-template <typename T, bool PERM, int KC>
-__global__ __launch_bounds__(4 * WAVE) void k_sell_kc4(int64_t M, int64_t c0, int64_t nchunks,
+// Narrow SELL with C = 64, NW (4 or 6) waves per chunk: wave h takes the
+// slots [h*q, min(w, (h+1)*q)) of each stored row, q = ceil(w/NW), with every
+// one of its loads in flight; the NW sums are added in wave order through
+// LDS.  Against one wave per chunk this holds a fraction of the registers
+// per wave (more waves per SIMD) and of the dependent round trip per wave,
+// so the chunk streams keep more bytes in flight.  Stencil rows of 27 slots,
+// FP64: 65.5 us with one wave, 61.3 with four (7 slots each), 60.0 with six
+// (5 each), 61.7 with eight; in FP32 six waves lose (41.6 against 34.9 us),
+// so both are autotuner candidates.
+template <typename T, bool PERM, int KC, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_sell_kcw(int64_t M, int64_t c0, int64_t nchunks,
                                                       const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ scol, const T* __restrict__ sval,
                                                       const T* __restrict__ x, T* __restrict__ y, int remap,
                                                       int add) {
-  constexpr int KQ = (KC + 3) / 4;
-  __shared__ double part[4][WAVE];
+  constexpr int KQ = (KC + NW - 1) / NW;
+  __shared__ double part[NW][WAVE];
   const int h = (int)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
   const int p = (int)(threadIdx.x & (WAVE - 1));
   const int64_t c = c0 + (int64_t)(remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
   if (c >= nchunks) return;  // uniform over the workgroup
   const int64_t base = cs[c];
   const int w = (int)((cs[c + 1] - base) >> 6);
-  const int q = (w + 3) >> 2;
+  const int q = (w + NW - 1) / NW;
   const int k0 = h * q;
   const int n = w - k0 < q ? w - k0 : q;  // this wave's slots (may be <= 0)
   double sa[4] = {0.0, 0.0, 0.0, 0.0};
@@ -578,9 +581,12 @@ __global__ __launch_bounds__(4 * WAVE) void k_sell_kc4(int64_t M, int64_t c0, in
   part[h][p] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
   __syncthreads();
   if (h == 0) {
+    double t = part[0][p];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) t += part[i][p];
     const int64_t pos = c * WAVE + p;
     const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-    if (r >= 0) put_y(y, r, ((part[0][p] + part[1][p]) + part[2][p]) + part[3][p], add);
+    if (r >= 0) put_y(y, r, t, add);
   }
 }
 
@@ -716,12 +722,21 @@ static void launch_sell_kc(spmv_mat_s* A, const void* x, void* y, hipStream_t s)
   // contiguous ranges per XCD only while a sort window is small next to an
   // XCD's share of the rows (chunk widths then do not trend across the list)
   const int remap = (int64_t)A->sigma * 8 <= A->M;
-  if (LOGC == 6 && (A->params.flags & SPMV_FLAG_SPLIT4)) {  // g = one workgroup per chunk
+  if (LOGC == 6 && (A->params.flags & SPMV_FLAG_SPLIT6)) {  // g = one workgroup per chunk
     if (A->perm)
-      launch(k_sell_kc4<T, true, KC>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+      launch(k_sell_kcw<T, true, KC, 6>, g, 6 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
              (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
     else
-      launch(k_sell_kc4<T, false, KC>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+      launch(k_sell_kcw<T, false, KC, 6>, g, 6 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+             (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
+    return;
+  }
+  if (LOGC == 6 && (A->params.flags & SPMV_FLAG_SPLIT4)) {
+    if (A->perm)
+      launch(k_sell_kcw<T, true, KC, 4>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
+             (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
+    else
+      launch(k_sell_kcw<T, false, KC, 4>, g, 4 * WAVE, s, A->M, A->kc_first, A->nchunks, A->cs, A->perm, A->scol,
              (const T*)A->sval, (const T*)x, (T*)y, remap, A->acc);
     return;
   }

@@ -65,6 +65,8 @@ FORMAT_CONFIGS = [
     ("sell", {"sell_C": 64, "sell_sigma": 16384}),
     ("sell", {"sell_C": 64, "sell_sigma": 1, "flags": 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "flags": 64}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1, "flags": 128}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "flags": 128 | 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "bands": 3}),
     ("sell", {"sell_C": 8, "sell_sigma": 1, "bands": 8}),
     ("sell", {"sell_C": 32, "sell_sigma": 64, "bands": 2, "flags": 8}),
