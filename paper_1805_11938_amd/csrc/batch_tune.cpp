@@ -5,6 +5,7 @@
 #include <new>
 #include <tuple>
 
+#include <algorithm>
 #include "common.h"
 
 namespace spmv {
@@ -217,8 +218,10 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       break;
     case SPMV_FMT_CSR5:
       for (int sg : {4, 8, 16, 32}) add([sg](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = 1; });
+      // over bands the short tiles win (zipf_1M over 2 bands: sigma 8 153.5 us,
+      // 4 154.2, 16 164.5: more waves in flight for the band's gathers)
       for (int nb : xbands)
-        for (int sg : {16, 32})
+        for (int sg : {4, 8, 16, 32})
           add([sg, nb](spmv_params_t& p) { p.csr5_omega = 64; p.csr5_sigma = sg; p.bands = nb; });
       break;
     case SPMV_FMT_ELL:
@@ -276,8 +279,12 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
       // zipf_1M's HYB from 191 to 159 us (8 MB of x), 4 bands rmat24's from
       // 3.59 to 2.17 ms (134 MB); on x of about 8 MB with shorter tails, and
       // in FP32 at 4 MB, bands lost.
+      // and K = 0, 1, 2: a short ELL part and nearly all entries in the
+      // banded tail (zipf_1M over 2 bands: K 1 158 us against 165 at K 3)
       std::vector<int32_t> Ks{-1};
       for (double q : {0.5, 0.75, 0.9, 0.99}) Ks.push_back(csr->M ? lens[(size_t)(q * (double)(csr->M - 1))] : 0);
+      for (int32_t k : {0, 1, 2})
+        if (std::find(Ks.begin(), Ks.end(), k) == Ks.end()) Ks.push_back(k);
       std::vector<int> nbs{1};
       const int64_t xbytes = csr->N * (int64_t)csr->sv;
       if (csr->M && xbytes > ((int64_t)4 << 20)) nbs.insert(nbs.end(), {2, 4});
