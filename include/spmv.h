@@ -268,14 +268,15 @@ spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int r
  * fastest into *inout.  CSR: row blocks, wave units, linear order, XCD
  * bands, wave tiles, V lanes per row, and, when x exceeds 4 MiB, row blocks
  * and wave tiles over 2 and 4 column bands.  CSR5: sigma in {4, 8, 16, 32};
- * when x exceeds 4 MiB also sigma 16 and 32 over 2 and 4 column bands (8 too
+ * when x exceeds 4 MiB each of them also over 2 and 4 column bands (8 too
  * above 32 MiB).  ELL: one wave or four waves per 64 rows.  SELL: C in {8,
  * 16, 32, 64} x sigma in {1, C, 8C, 256C, M} (M: one window over all rows),
- * C = 64 also with four waves per chunk, and, when x exceeds 4 MiB, C 32 and
- * 64 with sigma = M over 2 and 4 column bands (8 above 32 MiB).  HYB: K in
- * {rule, p50, p75, p90, p99}, each with one or four waves per 64 rows of the
- * ELL part and with the COO tail over 2 and 4 column bands when x exceeds
- * 4 MiB (8 above 32 MiB).  ms_out (optional) receives the best median.  The
+ * C = 64 also with four and with six waves per chunk, and, when x exceeds
+ * 4 MiB, C 32 and 64 with sigma = M over 2 and 4 column bands (8 above 32
+ * MiB).  HYB: K in {rule, p50, p75, p90, p99, 0, 1, 2}, each with one or four
+ * waves per 64 rows of the ELL part and with the COO tail over 2 and 4 column
+ * bands when x exceeds 4 MiB (8 above 32 MiB).  ms_out (optional) receives
+ * the best median.  The
  * result is cached for the life of the process, keyed by a 64-bit hash of
  * the sparsity structure (ptr, col), the shape, dtype, format, byte cap and
  * the caller's flags (the candidates keep the flags the grid does not set):
