@@ -54,6 +54,7 @@ FORMAT_CONFIGS = [
     ("csr5", {"bands": 3}),
     ("csr5", {"csr5_sigma": 4, "bands": 8}),
     ("csr5", {"csr5_sigma": 32, "bands": 2}),
+    ("csr5", {"csr5_sigma": 8, "bands": 2}),
     ("ell", {}),
     ("ell", {"flags": 4}),
     ("ell", {"flags": 64}),
@@ -67,6 +68,7 @@ FORMAT_CONFIGS = [
     ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "flags": 64}),
     ("sell", {"sell_C": 64, "sell_sigma": 1, "flags": 128}),
     ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "flags": 128 | 64}),
+    ("sell", {"sell_C": 64, "sell_sigma": 1, "flags": 128, "bands": 2}),
     ("sell", {"sell_C": 64, "sell_sigma": 1 << 30, "bands": 3}),
     ("sell", {"sell_C": 8, "sell_sigma": 1, "bands": 8}),
     ("sell", {"sell_C": 32, "sell_sigma": 64, "bands": 2, "flags": 8}),
