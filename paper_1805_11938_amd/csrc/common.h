@@ -207,6 +207,7 @@ struct spmv_mat_s {
   int32_t* tile_nzbase = nullptr;
   int64_t nchains = 0;
   int32_t* chains = nullptr;     // (row, t_begin, t_end) triples for the carry fix-up
+  int64_t nchains_short = 0;     // the first nchains_short chains span at most C5_SHORT tiles
   double* carry = nullptr;       // ntiles + 1 partial sums (run scratch)
 
   // Column bands (params.bands > 1, CSR, SELL and CSR5): sub[b] is the handle's

@@ -182,6 +182,29 @@ __global__ void k_c5_tail_rlo(int64_t M, int64_t TW, const int32_t* ptr, int32_t
   *out = (int32_t)lo;
 }
 
+// The carry fix-up takes chains of at most C5_SHORT tiles one per thread and
+// longer ones one per wave: short tiles (small sigma) make many short chains,
+// for which a wave each leaves 60 of 64 lanes idle (zipf_1M, sigma 4 over two
+// bands: 6.3 us per band pass with a wave per chain).  The chains are put
+// short first (each group in tile order); A->nchains_short counts them.
+constexpr int C5_SHORT = 32;
+
+static spmv_status_t c5_split_chains(spmv_mat_s* A, hipStream_t s) {
+  const int64_t n = A->nchains;
+  std::vector<int32_t> h((size_t)n * 3), o;
+  SPMV_TRY(copy_to_host(h.data(), A->chains, sizeof(int32_t) * h.size(), s));
+  o.reserve(h.size());
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t c = 0; c < n; ++c) {
+      const bool shrt = h[3 * c + 2] - h[3 * c + 1] < C5_SHORT;
+      if (shrt == (pass == 0)) o.insert(o.end(), {h[3 * c], h[3 * c + 1], h[3 * c + 2]});
+      if (pass == 0 && shrt) ++A->nchains_short;
+    }
+  SPMV_HIP(hipMemcpyAsync(A->chains, o.data(), sizeof(int32_t) * o.size(), hipMemcpyHostToDevice, s));
+  SPMV_HIP(hipStreamSynchronize(s));
+  return SPMV_OK;
+}
+
 spmv_status_t convert_csr5(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   const int64_t M = src->M, nnz = src->nnz;
   const int omega = A->params.csr5_omega, sigma = A->params.csr5_sigma;
@@ -260,6 +283,7 @@ spmv_status_t convert_csr5(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
   SPMV_TRY(copy_to_host(&A->tail_rlo, rlo.p, sizeof(int32_t), s));
   const int64_t Tlast = TW < nnz ? T : T - 1;  // last index with a tile_row of its own
   A->nchains = 0;
+  A->nchains_short = 0;
   if (Tlast >= 1) {
     DTmp head, pos;
     SPMV_TRY(head.alloc(sizeof(int32_t) * (Tlast + 1)));
@@ -275,6 +299,7 @@ spmv_status_t convert_csr5(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
       k_c5_chains<<<grid_n(Tlast + 1), BS, 0, s>>>(Tlast, head.as<int32_t>(), pos.as<int32_t>(), A->tile_row,
                                                    A->chains);
       SPMV_LAUNCH_CHECK();
+      SPMV_TRY(c5_split_chains(A, s));
     }
     SPMV_HIP(hipStreamSynchronize(s));
   }
@@ -502,6 +527,24 @@ __global__ __launch_bounds__(BS) void k_csr5_fix(int64_t nchains, const int32_t*
   if (__lane_id() == 0) y[row] = (T)((double)y[row] + s);
 }
 
+// one thread per chain of at most C5_SHORT tiles: its carries in tile order
+// (four loads in flight), then added onto the row
+template <typename T>
+__global__ __launch_bounds__(BS) void k_csr5_fix_short(int64_t nchains, const int32_t* __restrict__ chains,
+                                                       const double* __restrict__ carry, T* __restrict__ y) {
+  const int64_t c = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (c >= nchains) return;
+  const int32_t row = chains[3 * c], tb = chains[3 * c + 1], te = chains[3 * c + 2];
+  double s = 0.0;
+  int32_t u = tb;
+  for (; u + 3 <= te; u += 4) {
+    const double a = carry[u], b = carry[u + 1], d = carry[u + 2], e = carry[u + 3];
+    s = (((s + a) + b) + d) + e;
+  }
+  for (; u <= te; ++u) s += carry[u];
+  y[row] = (T)((double)y[row] + s);
+}
+
 template <typename T, bool EMPTY, bool W64, bool PY = false>
 static void launch_c5w(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
   switch (a.sigma) {
@@ -552,8 +595,14 @@ static spmv_status_t run_csr5_t(spmv_mat_s* A, const T* x, T* y, hipStream_t s) 
   if (A->has_empty) launch_c5<T, true>(a, grid, (const T*)A->val, x, y, s);
   else launch_c5<T, false>(a, grid, (const T*)A->val, x, y, s);
   SPMV_LAUNCH_CHECK();
-  if (A->nchains > 0) {
-    launch(k_csr5_fix<T>, (unsigned)cdiv(A->nchains, BS / WAVE), BS, s, A->nchains, A->chains, A->carry, y);
+  if (A->nchains_short > 0) {  // a thread per short chain
+    launch(k_csr5_fix_short<T>, (unsigned)cdiv(A->nchains_short, BS), BS, s, A->nchains_short, A->chains, A->carry,
+           y);
+    SPMV_LAUNCH_CHECK();
+  }
+  if (A->nchains > A->nchains_short) {  // a wave per long chain
+    const int64_t nl = A->nchains - A->nchains_short;
+    launch(k_csr5_fix<T>, (unsigned)cdiv(nl, BS / WAVE), BS, s, nl, A->chains + 3 * A->nchains_short, A->carry, y);
     SPMV_LAUNCH_CHECK();
   }
   return SPMV_OK;

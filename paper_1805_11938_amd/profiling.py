@@ -35,7 +35,7 @@ SCRUB = "k_scrub"
 COPY = "k_copy"
 # kernels that spmv_run launches (conversion, feature and selection kernels
 # run outside the scrubbed launches and are not counted)
-RUN_KERNELS = ("k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix",
+RUN_KERNELS = ("k_csr_rows", "k_csr_waves", "k_csr_long_fix", "k_csr_vector", "k_csr5", "k_csr5_fix", "k_csr5_fix_short",
                "k_ell", "k_ell2", "k_ell_kc", "k_ell_kc4", "k_sell", "k_sell_kc", "k_sell_kcw", "k_sell_mixed", "k_sell_fix",
                "k_coo_tiles", "k_tile_fix", "k_csr_tiles", "k_csr_spmm", "k_csr_batched", "k_batch_tile_fix")
 
