@@ -508,6 +508,29 @@ __device__ __forceinline__ void sell_slots(const int32_t* __restrict__ cc, const
   for (int u = 0; u < KW; ++u) sa[u & 3] += (u < w && cg[u] >= 0) ? (double)vg[u] * (double)xg[u] : 0.0;
 }
 
+// sell_slots for a column band after the first: the old y of the lane's row
+// (r < 0: none) is loaded beside the gathers, not after the sum.
+template <typename T, int LOGC, int KW>
+__device__ __forceinline__ double sell_slots_y(const int32_t* __restrict__ cc, const T* __restrict__ vv,
+                                               const T* __restrict__ x, int w, double* sa,
+                                               const T* __restrict__ y, int64_t r) {
+  constexpr int C = 1 << LOGC;
+  int32_t cg[KW];
+  T vg[KW], xg[KW];
+#pragma unroll
+  for (int u = 0; u < KW; ++u) cg[u] = ldnt32(cc, (uint32_t)((u < w ? u : w - 1) * C));
+#pragma unroll
+  for (int u = 0; u < KW; ++u) vg[u] = ldnt32(vv, (uint32_t)((u < w ? u : w - 1) * C));
+  issue_fence();
+  const T yo = y[r >= 0 ? r : 0];
+#pragma unroll
+  for (int u = 0; u < KW; ++u) xg[u] = ld32(x, (uint32_t)(cg[u] >= 0 ? cg[u] : 0));
+  issue_fence();
+#pragma unroll
+  for (int u = 0; u < KW; ++u) sa[u & 3] += (u < w && cg[u] >= 0) ? (double)vg[u] * (double)xg[u] : 0.0;
+  return (double)yo;
+}
+
 // Narrow SELL (chunks [c0, nchunks), each at most KC wide): one lane per
 // stored row, one pass over the chunks (no persistent loop).  A chunk runs
 // in the smallest of 4, 8, 16 and KC places that holds its width (with
@@ -646,8 +669,25 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
   const int64_t c = c0 + (LOGC == 6 ? (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(gid >> 6)) : gid >> LOGC);
   if (c >= nchunks) return;
   const int p = (int)(gid & (C - 1));
+  const int64_t pos = c * C + p;
+  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
   const int64_t base = cs[c];
   const int w = (int)((cs[c + 1] - base) >> LOGC);
+  if (add) {  // a band after the first: the old y loaded beside the gathers
+    double yo = 0.0;
+    if (w > 0) {
+      const int32_t* cc = scol + base + p;
+      const T* vv = sval + base + p;
+      if (KC > 16 && w > 16) yo = sell_slots_y<T, LOGC, KC>(cc, vv, x, w, sa, y, r);
+      else if (KC > 8 && w > 8) yo = sell_slots_y<T, LOGC, (KC < 16 ? KC : 16)>(cc, vv, x, w, sa, y, r);
+      else if (KC > 4 && w > 4) yo = sell_slots_y<T, LOGC, (KC < 8 ? KC : 8)>(cc, vv, x, w, sa, y, r);
+      else yo = sell_slots_y<T, LOGC, (KC < 4 ? KC : 4)>(cc, vv, x, w, sa, y, r);
+    } else if (r >= 0) {
+      yo = (double)y[r];
+    }
+    if (r >= 0) y[r] = (T)(yo + ((sa[0] + sa[1]) + (sa[2] + sa[3])));
+    return;
+  }
   if (w > 0) {
     const int32_t* cc = scol + base + p;
     const T* vv = sval + base + p;
@@ -656,8 +696,6 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
     else if (KC > 4 && w > 4) sell_slots<T, LOGC, (KC < 8 ? KC : 8)>(cc, vv, x, w, sa);
     else sell_slots<T, LOGC, (KC < 4 ? KC : 4)>(cc, vv, x, w, sa);
   }
-  const int64_t pos = c * C + p;
-  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
   if (r >= 0) put_y(y, r, (sa[0] + sa[1]) + (sa[2] + sa[3]), add);
 }
 
@@ -676,6 +714,10 @@ __global__ __launch_bounds__(BS) void k_sell_fix(int64_t M, int64_t nwide, int C
   const int t = threadIdx.x, S = BS / C, p = t % C, j = t / C;
   const int4 wd = wide[wi];  // chunk, first item, item count
   const double* q = part + (int64_t)wd.y * C + p;
+  // the row and, adding, its old y: loaded before the partial sums
+  const int64_t pos = (int64_t)wd.x * C + p;
+  const int64_t r = j == 0 ? (PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1)) : -1;
+  const double yo = add && r >= 0 ? (double)y[r] : 0.0;
   double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = j; i < wd.z; i += 8 * S) {
     double v[8];
@@ -692,9 +734,7 @@ __global__ __launch_bounds__(BS) void k_sell_fix(int64_t M, int64_t nwide, int C
   if (j == 0) {
     double sum = red[p];
     for (int jj = 1; jj < S; ++jj) sum += red[jj * C + p];
-    const int64_t pos = (int64_t)wd.x * C + p;
-    const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
-    if (r >= 0) put_y(y, r, sum, add);
+    if (r >= 0) y[r] = add ? (T)(yo + sum) : (T)sum;
   }
 }
 
