@@ -526,13 +526,14 @@ __global__ void k_tile_fix(int64_t ntiles, const double* __restrict__ head_part,
                            T* __restrict__ y) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
     if (tinfo[t] != TILE_TAIL) continue;
+    const int32_t r = tail_row[t];
+    const double yo = ADD ? (double)y[r] : 0.0;  // loaded before the partials, not after them
     double tot = tail_part[t];
     for (int64_t u = t + 1;; ++u) {
       tot += head_part[u];
       if (tinfo[u] != TILE_SPAN) break;
     }
-    const int32_t r = tail_row[t];
-    y[r] = ADD ? (T)((double)y[r] + tot) : (T)tot;
+    y[r] = ADD ? (T)(yo + tot) : (T)tot;
   }
 }
 
