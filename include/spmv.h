@@ -264,8 +264,9 @@ spmv_status_t spmv_gather_probe(int64_t nx, int64_t rows, spmv_dtype_t dt, int r
                                 spmv_stream_t s, double* ms);
 
 /* Not in the paper (it fixes each format's parameters; Sec. II-B names them).
- * Autotuner: time every candidate of fmt's grid on x/y and write the
- * fastest into *inout.  CSR: row blocks, wave units, linear order, XCD
+ * Autotuner: time every candidate of fmt's grid on x/y (reps launches each),
+ * time the three fastest again with 3 * reps launches, and write the fastest
+ * of that round into *inout.  CSR: row blocks, wave units, linear order, XCD
  * bands, wave tiles, V lanes per row, and, when x exceeds 4 MiB, row blocks
  * and wave tiles over 2 and 4 column bands.  CSR5: sigma in {4, 8, 16, 32};
  * when x exceeds 4 MiB each of them also over 2 and 4 column bands (8 too

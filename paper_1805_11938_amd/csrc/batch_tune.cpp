@@ -301,9 +301,12 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
     }
     default: return fail(SPMV_ERR_INVALID_ARG, "format %d", (int)fmt);
   }
-  double best = 1e300;
-  spmv_params_t bestp = base;
-  bool any = false;
+  // Every candidate is timed with `reps` launches; the three fastest are then
+  // timed again with three times as many, and the fastest of that round wins
+  // (one lucky median among dozens of candidates otherwise decides: rmat24's
+  // CSR over 2 bands was timed at 2.52 ms by the first round and runs at
+  // 2.78 ms, against 2.61 ms over 4 bands).
+  std::vector<std::pair<double, spmv_params_t>> scored;
   for (const spmv_params_t& p : cand) {
     spmv_mat_t B = nullptr;
     spmv_status_t cst = spmv_convert(csr, fmt, &p, s, &B);
@@ -314,13 +317,31 @@ spmv_status_t spmv_autotune(spmv_mat_t csr, spmv_fmt_t fmt, const void* x, void*
     const spmv_params_t used = B->params;
     spmv_mat_free(B);
     if (tst != SPMV_OK) return tst;
-    if (out[0] < best) {
-      best = out[0];
-      bestp = used;
-      any = true;
+    scored.emplace_back(out[0], used);
+  }
+  if (scored.empty()) return fail(SPMV_ERR_TOO_LARGE, "no candidate of format %d fits the byte cap", (int)fmt);
+  std::stable_sort(scored.begin(), scored.end(),
+                   [](const std::pair<double, spmv_params_t>& a, const std::pair<double, spmv_params_t>& b) {
+                     return a.first < b.first;
+                   });
+  double best = scored[0].first;
+  spmv_params_t bestp = scored[0].second;
+  if (scored.size() > 1) {
+    best = 1e300;
+    const int r3 = 3 * std::max(reps, 1);
+    for (size_t i = 0; i < std::min<size_t>(3, scored.size()); ++i) {
+      spmv_mat_t B = nullptr;
+      SPMV_TRY(spmv_convert(csr, fmt, &scored[i].second, s, &B));
+      double out[5];
+      spmv_status_t tst = time_run(B, x, y, 2, r3, r3, 0.0, scrub_bytes, st, out);
+      spmv_mat_free(B);
+      if (tst != SPMV_OK) return tst;
+      if (out[0] < best) {
+        best = out[0];
+        bestp = scored[i].second;
+      }
     }
   }
-  if (!any) return fail(SPMV_ERR_TOO_LARGE, "no candidate of format %d fits the byte cap", (int)fmt);
   *inout = bestp;
   if (ms_out) *ms_out = best;
   std::lock_guard<std::mutex> g(g_tune_mu);
