@@ -133,8 +133,6 @@ __global__ void k_c5_erows(int64_t M, const int32_t* ptr, const int32_t* rank, i
     if (ptr[r + 1] == ptr[r]) erows[r - rank[r]] = (int32_t)r;
 }
 
-// y = 0 on the empty rows (the tiles write only rows that own entries)
-
 __global__ void k_c5_nzbase(int64_t T, const int32_t* tile_ptr, const int32_t* rank, int32_t* base) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (int64_t)gridDim.x * blockDim.x)
     base[t] = rank[tile_ptr[t]];
@@ -415,7 +413,7 @@ __device__ __forceinline__ void c5_tile(const C5Args& a, int64_t t, int l, const
   int32_t rp[C5_PY] = {0, 0, 0, 0};
   int nw = 0;  // rows (or the carry) written so far
   auto put = [&](int j, double sum) {
-    if (PY && nw < C5_PY && !(j == 0 && cont)) {
+    if (PY && SIG > 0 && nw < C5_PY && !(j == 0 && cont)) {  // (the prefetch is in the SIG > 0 path)
       const int64_t r = EMPTY ? (int64_t)rp[0] : row0 + j;
       y[r] = (T)(yp[0] + sum);
     } else {
@@ -558,9 +556,10 @@ static void launch_c5w(const C5Args& a, unsigned grid, const T* val, const T* x,
 
 template <typename T, bool EMPTY>
 static void launch_c5(const C5Args& a, unsigned grid, const T* val, const T* x, T* y, hipStream_t s) {
-  // adding onto y: the old values prefetched (sigma <= 16; with sigma = 32
-  // the extra registers cost more than the dependent loads they save)
-  if (a.omega == WAVE && a.add && a.sigma <= 16) launch_c5w<T, EMPTY, true, true>(a, grid, val, x, y, s);
+  // adding onto y: the old values prefetched (sigma 4, 8 and 16; with sigma =
+  // 32 the extra registers cost more than the dependent loads they save)
+  if (a.omega == WAVE && a.add && (a.sigma == 4 || a.sigma == 8 || a.sigma == 16))
+    launch_c5w<T, EMPTY, true, true>(a, grid, val, x, y, s);
   else if (a.omega == WAVE) launch_c5w<T, EMPTY, true>(a, grid, val, x, y, s);
   else launch_c5w<T, EMPTY, false>(a, grid, val, x, y, s);
 }

@@ -55,6 +55,7 @@ FORMAT_CONFIGS = [
     ("csr5", {"csr5_sigma": 4, "bands": 8}),
     ("csr5", {"csr5_sigma": 32, "bands": 2}),
     ("csr5", {"csr5_sigma": 8, "bands": 2}),
+    ("csr5", {"csr5_sigma": 5, "bands": 2}),
     ("ell", {}),
     ("ell", {"flags": 4}),
     ("ell", {"flags": 64}),
