@@ -6,6 +6,7 @@
   the failed conversion leaves no device memory behind;
 * freed arrays are kept and handed out again (a second conversion reuses
   them, with identical results) and spmv_mem_release returns them to HIP;
+  with SPMV_CACHE_BYTES=0 nothing is kept;
 * the autotuner's cache keeps callers with different flags apart;
 * the selector falls back to exhaustive profiling when the network predicts a
   format that cannot hold the matrix (ELL over the byte cap).
@@ -127,6 +128,38 @@ def test_freed_blocks_are_reused_and_released(torch):
     assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
     yref, den = reference(A, synth.vector(A.N, 4), 0)
     assert rowwise_err(outs[0], yref, den) <= TOL[0]
+
+
+_NOCACHE_SCRIPT = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_1805_11938_amd import spmv as S, synth
+L = S.lib()
+assert torch.cuda.is_available()
+A = synth.stencil27(12, 2)
+H = S.Matrix.from_host(A)
+x = torch.from_numpy(synth.vector(A.N, 4)).cuda()
+before = L.spmv_mem_in_use()
+ys = []
+for _ in range(2):
+    B = H.convert("sell", sell_C=64, sell_sigma=1, flags=128)
+    ys.append(B.run(x).cpu().numpy().tolist())
+    del B
+print(json.dumps(dict(before=before, end=L.spmv_mem_in_use(), released=L.spmv_mem_release(), same=ys[0] == ys[1])))
+"""
+
+
+def test_cache_disabled_keeps_nothing(torch):
+    """SPMV_CACHE_BYTES=0: freed arrays go straight back to HIP, so there is
+    nothing to release, and results are unchanged."""
+    env = dict(os.environ, SPMV_CACHE_BYTES="0")
+    print("subprocess: SPMV_CACHE_BYTES=0, two SELL conversions", flush=True)
+    r = subprocess.run([sys.executable, "-c", _NOCACHE_SCRIPT, ROOT], env=env, capture_output=True, text=True,
+                       timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["end"] == out["before"] and out["released"] == 0 and out["same"], out
 
 
 def test_autotune_cache_keeps_flags_apart(torch):
