@@ -760,8 +760,9 @@ spmv_status_t run_csr(spmv_mat_s* A, const void* x, void* y, hipStream_t s) {
 // VEC > 1 needs k, ldx and ldy multiples of VEC and 16-byte aligned X and
 // Y; otherwise VEC = 1.
 //
-// Blocks: when every row is short enough (rb rows of the longest row fit
-// the LDS staging), blocks of rb = max(G, 64) rows, G = BS / (k/VEC) rows in
+// Blocks: when every row is short enough (rb rows of the longest row, plus
+// the 3 entries staging may start below a block's first one, fit the LDS
+// staging), blocks of rb = max(G, 64) rows, G = BS / (k/VEC) rows in
 // flight per workgroup, so every pass over the rows keeps all lanes busy;
 // otherwise the row blocks of the SpMV kernel (rows + nonzeros <= CSR_W).
 constexpr int SPMM_CAP = 2048;  // entries a block stages in LDS
@@ -787,16 +788,67 @@ __device__ __forceinline__ void spmm_store(T* p, const VecN<T, VEC>& o) {
   }
 }
 
+// Entries [s0, s0 + E) of col and val (s0 a multiple of 4, E <= SPMM_CAP)
+// into LDS with 16-byte loads, all in flight before the LDS stores; the
+// vector that would reach past the last entry of the matrix is loaded entry
+// by entry.  col and val are 16-byte aligned (device allocations).
+template <typename T>
+__device__ __forceinline__ void spmm_stage(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t s0,
+                                           int64_t E, int64_t nnz, int32_t* scol, T* sval, int t) {
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  constexpr int VPV = 16 / sizeof(T);          // values per 16-byte vector
+  constexpr int NC = SPMM_CAP / 4 / BS;        // column vectors per thread
+  constexpr int NV = SPMM_CAP / VPV / BS;      // value vectors per thread
+  i4 cv[NC], vv[NV];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int64_t e0 = 4 * (int64_t)(t + j * BS);
+    if (e0 < E) {
+      if (s0 + e0 + 4 <= nnz) {
+        cv[j] = __builtin_nontemporal_load((const i4*)(col + s0 + e0));
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cv[j][i] = col[s0 + e0 + i < nnz ? s0 + e0 + i : nnz - 1];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int64_t e0 = (int64_t)VPV * (t + j * BS);
+    if (e0 < E) {
+      if (s0 + e0 + VPV <= nnz) {
+        vv[j] = __builtin_nontemporal_load((const i4*)(val + s0 + e0));
+      } else {
+        T w[VPV];
+#pragma unroll
+        for (int i = 0; i < VPV; ++i) w[i] = val[s0 + e0 + i < nnz ? s0 + e0 + i : nnz - 1];
+        __builtin_memcpy(&vv[j], w, 16);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int e0 = 4 * (t + j * BS);
+    if (e0 < E) *(i4*)(scol + e0) = cv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int e0 = VPV * (t + j * BS);
+    if (e0 < E) *(i4*)(sval + e0) = vv[j];
+  }
+}
+
 template <typename T, int VEC>
 __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __restrict__ blk_row, int rb,
                                                  int64_t M, const int32_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ X, int64_t ldx, T* __restrict__ Y,
-                                                 int64_t ldy, int k) {
+                                                 int64_t ldy, int k, int64_t nnz) {
   typedef VecN<T, VEC> V;
   // staged entries; the long-row path's partial sums reuse the same bytes
   static_assert(SPMM_CAP * (4 + sizeof(T)) >= BS * VEC * sizeof(double), "LDS reuse");
   __shared__ __align__(16) char lds[SPMM_CAP * (4 + sizeof(T))];
+  __shared__ int32_t sptr[BS + 1];  // row pointers of a block of at most BS rows (fixed-size blocks)
   int32_t* scol = (int32_t*)lds;
   T* sval = (T*)(lds + SPMM_CAP * 4);
   double* red = (double*)lds;
@@ -810,55 +862,59 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
   const int64_t r0 = rb ? b * rb : blk_row[b];
   const int64_t r1 = rb ? (r0 + rb < M ? r0 + rb : M) : blk_row[b + 1];
   if (r0 >= r1) return;
-  const int64_t k0 = ptr[r0], E = ptr[r1] - k0;
+  // the block's entries are staged from the 4-entry boundary at or below
+  // its first one, so every staging load moves 16 bytes
+  const int64_t k1 = ptr[r1], s0 = ptr[r0] & ~(int64_t)3, E = k1 - s0;
   if (E <= SPMM_CAP) {
-    if (E > 0) {  // all staging loads in flight (clamped, branch-free), then the LDS stores
-      int32_t cs[SPMM_CAP / BS];
-      T vs[SPMM_CAP / BS];
-      const uint32_t Em1 = (uint32_t)E - 1;
-#pragma unroll
-      for (int j = 0; j < SPMM_CAP / BS; ++j) {
-        const uint32_t q = (uint32_t)(t + j * BS), qq = q < (uint32_t)E ? q : Em1;
-        cs[j] = ldnt32(col + k0, qq);
-        vs[j] = ldnt32(val + k0, qq);
-      }
-#pragma unroll
-      for (int j = 0; j < SPMM_CAP / BS; ++j) {
-        const int q = t + j * BS;
-        if (q < E) {
-          scol[q] = cs[j];
-          sval[q] = vs[j];
-        }
-      }
-    }
+    // fixed-size blocks (rb <= BS rows) read their row pointers from LDS
+    if (rb)
+      for (int i = t; i <= r1 - r0; i += BS) sptr[i] = ptr[r0 + i] - (int32_t)s0;
+    if (k1 > s0) spmm_stage<T>(col, val, s0, E, nnz, scol, sval, t);
     __syncthreads();
     if (g < G)
       for (int64_t r = r0 + g; r < r1; r += G) {
-        const int a = ptr[r] - (int32_t)k0, e = ptr[r + 1] - (int32_t)k0;
+        const int a = rb ? sptr[r - r0] : ptr[r] - (int32_t)s0, e = rb ? sptr[r - r0 + 1] : ptr[r + 1] - (int32_t)s0;
         double s2[2][VEC];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int v = 0; v < VEC; ++v) s2[i][v] = 0.0;
-        // SPMM_NB nonzeros at a time, all their gathers of X rows in flight;
-        // the last group repeats entry e-1 for its unused places and masks them
-        for (int q = a; q < e; q += SPMM_NB) {
-          const int n = e - q < SPMM_NB ? e - q : SPMM_NB;
-          int32_t cq[SPMM_NB];
+        // SPMM_NB nonzeros at a time, all their gathers of X rows in flight
+        int q = a;
+        for (; q + SPMM_NB <= e; q += SPMM_NB) {
           T vq[SPMM_NB];
           V xq[SPMM_NB];
 #pragma unroll
           for (int u = 0; u < SPMM_NB; ++u) {
-            const int qq = q + (u < n ? u : n - 1);
-            cq[u] = scol[qq];
-            vq[u] = sval[qq];
+            vq[u] = sval[q + u];
+            xq[u] = *(const V*)(X + (int64_t)scol[q + u] * ldx + c);
           }
-#pragma unroll
-          for (int u = 0; u < SPMM_NB; ++u) xq[u] = *(const V*)(X + (int64_t)cq[u] * ldx + c);
 #pragma unroll
           for (int u = 0; u < SPMM_NB; ++u)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) s2[u & 1][v] += u < n ? (double)vq[u] * (double)xq[u].v[v] : 0.0;
+            for (int v = 0; v < VEC; ++v) s2[u & 1][v] += (double)vq[u] * (double)xq[u].v[v];
+        }
+        // the last n < SPMM_NB nonzeros: a gather no lane of the wave needs
+        // is not issued (every vector-memory instruction costs address and
+        // data cycles whatever it moves)
+        if (q < e) {
+          const int n = e - q;
+          T vq[SPMM_NB - 1];
+          V xq[SPMM_NB - 1];
+#pragma unroll
+          for (int u = 0; u < SPMM_NB - 1; ++u) {
+            vq[u] = (T)0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) xq[u].v[v] = (T)0;
+            if (u < n) {
+              vq[u] = sval[q + u];
+              xq[u] = *(const V*)(X + (int64_t)scol[q + u] * ldx + c);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < SPMM_NB - 1; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s2[u & 1][v] += (double)vq[u] * (double)xq[u].v[v];
         }
         V out;
 #pragma unroll
@@ -901,14 +957,15 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
 template <typename T, int VEC>
 static void launch_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, hipStream_t s) {
   const int64_t G = BS / (k / VEC);
-  const int64_t rb = std::max<int64_t>(G, 64);
-  if (A->maxlen >= 0 && rb * std::max<int64_t>(A->maxlen, 1) <= SPMM_CAP) {
+  const int64_t rb = std::max<int64_t>(G, 64);  // at most BS: the kernel's LDS row pointers
+  // (+3: staging starts at the 4-entry boundary below a block's first entry)
+  if (A->maxlen >= 0 && rb * std::max<int64_t>(A->maxlen, 1) + 3 <= SPMM_CAP) {
     const int64_t nb = cdiv(A->M, rb);  // blocks of rb rows
     launch(k_csr_spmm<T, VEC>, (unsigned)nb, BS, s, nb, (const int32_t*)nullptr, (int)rb, A->M, A->ptr, A->col,
-           (const T*)A->val, (const T*)X, ldx, (T*)Y, ldy, k);
+           (const T*)A->val, (const T*)X, ldx, (T*)Y, ldy, k, A->nnz);
   } else {  // the SpMV kernel's row blocks
     launch(k_csr_spmm<T, VEC>, (unsigned)A->nblk, BS, s, A->nblk, (const int32_t*)A->blk_row, 0, A->M, A->ptr,
-           A->col, (const T*)A->val, (const T*)X, ldx, (T*)Y, ldy, k);
+           A->col, (const T*)A->val, (const T*)X, ldx, (T*)Y, ldy, k, A->nnz);
   }
 }
 
@@ -916,6 +973,8 @@ spmv_status_t run_spmm(spmv_mat_s* A, const void* X, int64_t ldx, void* Y, int64
   if (A->fmt != SPMV_FMT_CSR || !A->sub.empty()) return fail(SPMV_ERR_UNSUPPORTED, "spmm runs on CSR handles without column bands");
   if (k < 1 || k > 64 || ldx < k || ldy < k) return fail(SPMV_ERR_INVALID_ARG, "spmm needs 1 <= k <= 64, ld >= k");
   if (A->M == 0) return SPMV_OK;
+  if (((uintptr_t)A->col & 15) || ((uintptr_t)A->val & 15))
+    return fail(SPMV_ERR_UNSUPPORTED, "spmm stages col and val with 16-byte loads: arrays must be 16-byte aligned");
   // 16-byte lanes (2 FP64 or 4 FP32 columns) where k, the leading
   // dimensions and the alignment of X and Y allow, else one value per lane.
   // (32-byte lanes, two loads each, measured slower on the stencil.)

@@ -73,22 +73,23 @@ def test_spmm_wide_lanes(torch, dt, k, ldx, ldy):
 
 def _spmm_block_case(kind):
     """Row-length patterns around the SpMM block rule: blocks of max(G, 64)
-    rows are taken when that many rows of the longest row fit the 2,048
-    staged entries (k = 8 and 16 in FP64: 64 rows, so rows of up to 32;
-    k = 4: 128 rows of up to 16), else the SpMV row blocks.  M = 1,000
+    rows are taken when that many rows of the longest row, plus the 3
+    entries staging may start below a block's first one, fit the 2,048
+    staged entries (k = 8 and 16 in FP64: 64 rows, so rows of up to 31;
+    k = 4: 128 rows of up to 15), else the SpMV row blocks.  M = 1,000
     leaves a ragged last block."""
     M, N = 1000, 3000
     rng = np.random.default_rng(7)
     lens = rng.integers(0, 20, M).astype(np.int32)
-    if kind == "max32":          # the rule's limit: 64 x 32 = 2,048 entries
-        lens[rng.choice(M, 40, replace=False)] = 32
-        lens[64:128] = 32        # one whole block at the limit
-    elif kind == "max33":        # one row past it: the SpMV row blocks
-        lens[rng.choice(M, 40, replace=False)] = 32
-        lens[500] = 33
-    elif kind == "max16":        # k = 4 (128-row blocks) at its limit: 128 x 16
-        lens = rng.integers(0, 17, M).astype(np.int32)
-        lens[128:256] = 16
+    if kind == "max31":          # the rule's limit: 64 x 31 + 3 <= 2,048 entries
+        lens[rng.choice(M, 40, replace=False)] = 31
+        lens[64:128] = 31        # one whole block at the limit
+    elif kind == "max32":        # one past it: the SpMV row blocks
+        lens[rng.choice(M, 40, replace=False)] = 31
+        lens[500] = 32
+    elif kind == "max15":        # k = 4 (128-row blocks) at its limit: 128 x 15
+        lens = rng.integers(0, 16, M).astype(np.int32)
+        lens[128:256] = 15
     elif kind == "empty_blocks":  # whole blocks without entries, then entries
         lens[:256] = 0
         lens[900:] = 0
@@ -96,7 +97,7 @@ def _spmm_block_case(kind):
 
 
 @pytest.mark.parametrize("k", [4, 8, 16])
-@pytest.mark.parametrize("kind", ["max32", "max33", "max16", "empty_blocks"])
+@pytest.mark.parametrize("kind", ["max31", "max32", "max15", "empty_blocks"])
 def test_spmm_block_rule_edges(torch, kind, k):
     A = _spmm_block_case(kind)
     X = synth.uniform(A.N * k, 40 + k, -1.0, 1.0).reshape(A.N, k)
