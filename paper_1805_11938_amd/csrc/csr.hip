@@ -873,7 +873,8 @@ __global__ __launch_bounds__(BS) void k_csr_spmm(int64_t nblk, const int32_t* __
     __syncthreads();
     if (g < G)
       for (int64_t r = r0 + g; r < r1; r += G) {
-        const int a = rb ? sptr[r - r0] : ptr[r] - (int32_t)s0, e = rb ? sptr[r - r0 + 1] : ptr[r + 1] - (int32_t)s0;
+        const int a = rb ? sptr[r - r0] : ptr[r] - (int32_t)s0;
+        const int e = rb ? sptr[r - r0 + 1] : ptr[r + 1] - (int32_t)s0;
         double s2[2][VEC];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
