@@ -314,7 +314,33 @@ def bench_spmm(args):
            "per_k": per}
     if args.copy_probe:
         out["copy_probe_GBps"] = round(S.copy_probe(1 << 30, 20), 1)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_spmm(A, sv)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_spmm(A, sv, rows=100_000, min_s=3.0, budget_s=8.0):
+    """The oracle's SpMM (a single-threaded C loop over rows, nonzeros and
+    columns) on the first `rows` rows of the matrix, for k = 8 and 16 with
+    the benchmark's X; bytes by the same model as the GPU launches, with the
+    X rows the sample reads."""
+    import oracle
+    from paper_1805_11938_amd import synth
+    ms = min(rows, A.M)
+    nz = int(A.ptr[ms])
+    ptr, col, val = A.ptr[:ms + 1], A.col[:nz], A.val[:nz]
+    ncols = len(np.unique(col))
+    tot_b, tot_t, reps = 0, 0.0, 0
+    for k in (8, 16):
+        X = synth.uniform(A.N * k, 9, -1.0, 1.0).reshape(A.N, k)
+        ts, _ = _ci_timed(lambda: oracle.csr_spmm(ms, ptr, col, val, X), min_s, budget_s)
+        tot_b += nz * (sv + 4) + 4 * (ms + 1) + ncols * k * sv + ms * k * sv
+        tot_t += float(np.median(ts))
+        reps += len(ts)
+    return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"rows 0..{ms - 1} of the stencil ({nz} nonzeros), Y = A X for k = 8 and 16 (the oracle's "
+                      f"single-threaded C loop), median of {reps} calls in all",
+            "ms_per_step": round(1e3 * tot_t, 3)}
 
 
 def main():
