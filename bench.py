@@ -226,9 +226,11 @@ def bench_batch(args):
     dt = S.F64 if args.dtype == "f64" else S.F32
     tdt = torch.float64 if dt == S.F64 else torch.float32
     t0 = time.time()
-    mats, xs, ys, bmin, nnz = [], [], [], 0, 0
+    mats, xs, ys, bmin, nnz, cpu_work = [], [], [], 0, 0, []
     for i, spec in enumerate(synth.batch_specs(512, seed=8)):
         A = synth.make(spec)
+        if i % 4 == 0 and not args.no_cpu:  # the CPU baseline's sample: every fourth matrix
+            cpu_work.append((f"m{i}", A.M, A.ptr, A.col, A.val, synth.vector(A.N, 50 + i)))
         val = A.val.astype(np.float32) if dt == S.F32 else A.val
         mats.append(S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val, dt))
         xs.append(torch.from_numpy(synth.vector(A.N, 50 + i)).to("cuda", tdt))
@@ -263,6 +265,13 @@ def bench_batch(args):
            "speedup_vs_per_matrix": round(t1 / t, 3), "item_formats": kinds}
     if args.copy_probe:
         out["copy_probe_GBps"] = round(S.copy_probe(1 << 30, 20), 1)
+    if cpu_work:
+        cb = cpu_baseline(cpu_work, 8 if dt == S.F64 else 4)
+        cb["sample"] = (f"every fourth matrix of the batch ({len(cpu_work)} of 512, "
+                        f"{sum(len(w[3]) for w in cpu_work)} nonzeros), y=Ax over each per pass (FP64 CSR loop, "
+                        f"OpenMP static rows over {cb['cores']} threads), median of {cb['reps']} passes; "
+                        f"95% CI +-{100 * cb['ci_rel']:.1f}%")
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
