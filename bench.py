@@ -122,13 +122,15 @@ def selector_choices(bases, per, dname):
     model = S.Model.load(path)
     out = {}
     for name, base in bases.items():
+        t = {f: per[f"{name}/{f}"]["ms"] for f in S.FMT_NAMES if f"{name}/{f}" in per}
+        if not t:  # no format of this matrix was timed (--only)
+            continue
         fmt, _ = SEL.choose(base, model)
         inside = SEL.in_domain(base, model)
         w0 = time.perf_counter()
         for _ in range(10):  # features + inference, both synchronous
             SEL.choose(base, model)
         ov = (time.perf_counter() - w0) / 10 * 1e3
-        t = {f: per[f"{name}/{f}"]["ms"] for f in S.FMT_NAMES if f"{name}/{f}" in per}
         best = min(t, key=t.get)
         model_frac = round(t[best] / t[fmt], 4) if fmt in t else 0.0
         if inside:
@@ -140,9 +142,10 @@ def selector_choices(bases, per, dname):
             cost = sum(per[f"{name}/{f}"]["convert_ms"] + 20 * t[f] for f in t)
             r = {"how": "exhaustive (features outside the model's training range)", "chosen": best,
                  "frac_of_best": 1.0, "overhead_ms": round(cost, 3)}
-        r.update({"best": best, "model_choice": fmt, "model_frac_of_best": model_frac,
-                  "csr_frac_of_best": round(t[best] / t["csr"], 4),
-                  "overhead_in_csr_spmvs": round(r["overhead_ms"] / t["csr"], 2)})
+        r.update({"best": best, "model_choice": fmt, "model_frac_of_best": model_frac})
+        if "csr" in t:
+            r.update({"csr_frac_of_best": round(t[best] / t["csr"], 4),
+                      "overhead_in_csr_spmvs": round(r["overhead_ms"] / t["csr"], 2)})
         out[name] = r
     rep = os.path.join(SEL.DATA_DIR, "selector_report.json")
     if os.path.exists(rep):
