@@ -132,7 +132,7 @@ def selector_choices(bases, per, dname):
             SEL.choose(base, model)
         ov = (time.perf_counter() - w0) / 10 * 1e3
         best = min(t, key=t.get)
-        model_frac = round(t[best] / t[fmt], 4) if fmt in t else 0.0
+        model_frac = round(t[best] / t[fmt], 4) if fmt in t else None  # chosen format not timed (--only)
         if inside:
             r = {"how": "model", "chosen": fmt, "frac_of_best": model_frac, "overhead_ms": round(ov, 4)}
         else:
