@@ -150,3 +150,20 @@ def test_spmm_stencil_full(torch, k):
     for c in range(k):
         den = oracle.csr_absspmv(A.M, A.ptr, A.col, A.val, X[:, c].copy())
         assert rowwise_err(Y[:, c], Yref[:, c], den) <= TOL[0], c
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("k", [6, 16])
+def test_spmm_stencil_full_f32(torch, k):
+    """FP32 at full size: k = 16 takes 16-byte lanes of 4 values (6 nonzeros
+    per step), k = 6 one value per lane (9 per step)."""
+    A, _ = workload("stencil27_100")
+    val32 = A.val.astype(np.float32)
+    X = synth.uniform(A.N * k, 19, -1.0, 1.0).reshape(A.N, k).astype(np.float32)
+    X64 = X.astype(np.float64)
+    Yref = oracle.csr_spmm(A.M, A.ptr, A.col, val32.astype(np.float64), X64)
+    Ad = S.Matrix.from_csr(A.M, A.N, A.ptr, A.col, val32, S.F32)
+    Y = Ad.spmm(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    for c in range(k):
+        den = oracle.csr_absspmv(A.M, A.ptr, A.col, val32.astype(np.float64), X64[:, c].copy())
+        assert rowwise_err(Y[:, c], Yref[:, c], den) <= TOL[1], c
