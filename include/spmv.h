@@ -23,7 +23,7 @@
  *   the caller's arrays, so the caller may free them afterwards.  Runs of
  *   distinct handles on different streams are independent.  Three kinds of
  *   handle keep per-handle device scratch that every run rewrites -- CSR5
- *   (tile carries), SELL with column slices (partial sums) and CSR built
+ *   (tile carries), SELL with column slices (partial sums and slice counts) and CSR built
  *   with SPMV_FLAG_CSR_WAVES (long-row segment sums) -- so two runs of the
  *   *same* such handle must not overlap (same stream, or synchronise).
  *   x, y, X, Y stay owned by the caller: device pointers of the handle's

@@ -169,13 +169,14 @@ struct spmv_mat_s {
   int64_t* cs = nullptr;    // nchunks + 1 slot offsets
   int32_t* scol = nullptr;
   void* sval = nullptr;
-  int64_t nitems = 0, nwide = 0;  // column-slice work items; chunks split into several slices
+  int64_t nitems = 0, nwide = 0;  // column-slice work items; chunks split into more than SELL_FUSE slices
   int32_t sell_maxw = 0;          // widest chunk (= longest row)
   int64_t kc_first = 0;           // chunks [kc_first, nchunks) are at most SELL_KC_MAX wide (one-pass kernel);
   int32_t kc_w = 0;               // the widest of them; chunks before kc_first go through the slice items
   int2* items = nullptr;          // (chunk, first column) per item
   int4* wide = nullptr;           // (chunk, first item, item count) per split chunk
   double* part = nullptr;         // nitems * C partial sums (run scratch, split chunks only)
+  int32_t* wcnt = nullptr;        // per item: slices of its split chunk done (at the chunk's first item)
 
   // HYB COO part (row-major) and the per-tile scratch of its pass
   int64_t ncoo = 0;

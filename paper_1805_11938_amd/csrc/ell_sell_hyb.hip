@@ -482,9 +482,13 @@ __global__ void k_sell_to_csr(int64_t M, int64_t Mpad, int C, const int32_t* per
 
 // A work item is a slice of at most SELL_KT columns of one chunk, run by C
 // lanes (one per stored row).  Chunks of one slice write y directly; wider
-// chunks write per-slice partial sums that k_sell_fix adds in slice order.
-// The items run in k_sell_mixed, beside the narrow chunks.
+// chunks write per-slice partial sums.  For a chunk of at most SELL_FUSE
+// slices the item that finishes last (counted with an atomic) adds them in
+// slice order and writes y; longer chunks (rows of more than 8,192 entries)
+// leave that to k_sell_fix, a workgroup per chunk.  The items run in
+// k_sell_mixed, beside the narrow chunks.
 constexpr int SELL_KT = 64;
+constexpr int SELL_FUSE = 128;
 constexpr int SELL_KC_MAX = 32;  // widest chunk the one-pass narrow kernel takes
 
 // The slots of one stored row, KW places (KW >= w): every slot's column and
@@ -613,6 +617,42 @@ __global__ __launch_bounds__(NW * WAVE) void k_sell_kcw(int64_t M, int64_t c0, i
   }
 }
 
+// The slice item of a split chunk (at most SELL_FUSE slices) that finishes
+// last.  Each item stores its partial sums with agent-scope atomic stores
+// (written through to where every XCD reads them), waits until they are
+// done, then counts itself; the item that brings the count to nsl reads the
+// chunk's nsl partial sums of its row with agent-scope atomic loads, in
+// slice order, writes y and clears the count for the next run.  (Fences
+// would write back and invalidate a whole XCD's L2 for every item.)  Lanes
+// of one item are C consecutive lanes.
+template <typename T, int LOGC, bool PERM>
+__device__ __forceinline__ void sell_fix_last(int64_t M, int64_t first, int64_t it, int64_t nsl, int64_t c, int p,
+                                              double s, double* part, const int32_t* __restrict__ perm,
+                                              int32_t* cnt, T* __restrict__ y, int add) {
+  constexpr int C = 1 << LOGC;
+  __hip_atomic_store(part + it * C + p, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);  // the store has completed before the item is counted
+  int last = 0;
+  if (p == 0) last = __hip_atomic_fetch_add(cnt + first, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)nsl - 1;
+  last = __shfl(last, (int)(threadIdx.x & ~(unsigned)(C - 1)));
+  if (!last) return;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t j = 0; j < nsl; j += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = j + u < nsl ? __hip_atomic_load(part + (first + j + u) * C + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u];
+  }
+  const double sum = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  const int64_t pos = c * C + p;
+  const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
+  if (r >= 0) put_y(y, r, sum, add);
+  if (p == 0) cnt[first] = 0;
+}
+
 // SELL with wide chunks, one launch: the first nwg_wide workgroups (one wave
 // each) take the column slices of the chunks before kc_first (64 slots of one
 // chunk per item, C lanes per item), the rest the narrow chunks [c0, nchunks)
@@ -626,7 +666,7 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
                                                      const int64_t* __restrict__ cs, const int32_t* __restrict__ perm,
                                                      const int32_t* __restrict__ scol, const T* __restrict__ sval,
                                                      const T* __restrict__ x, T* __restrict__ y,
-                                                     double* __restrict__ part, int remap, int add) {
+                                                     double* part, int32_t* cnt, int remap, int add) {
   constexpr int C = 1 << LOGC;
   double sa[4] = {0.0, 0.0, 0.0, 0.0};
   if ((int64_t)blockIdx.x < nwg_wide) {
@@ -660,7 +700,9 @@ __global__ __launch_bounds__(WAVE) void k_sell_mixed(int64_t M, int64_t nitems, 
       const int64_t r = PERM ? (int64_t)perm[pos] : (pos < M ? pos : -1);
       if (r >= 0) put_y(y, r, s, add);
     } else {
-      part[it * C + p] = s;
+      const int64_t nsl = (w + SELL_KT - 1) / SELL_KT;
+      if (nsl <= SELL_FUSE) sell_fix_last<T, LOGC, PERM>(M, it - k0 / SELL_KT, it, nsl, c, p, s, part, perm, cnt, y, add);
+      else part[it * C + p] = s;
     }
     return;
   }
@@ -746,10 +788,10 @@ static void launch_sell_mixed(spmv_mat_s* A, const void* x, void* y, hipStream_t
   const unsigned g = (unsigned)(nwide + nnarrow);
   if (A->perm)
     launch(k_sell_mixed<T, LOGC, true, KC>, g, WAVE, s, A->M, A->nitems, A->items, nwide, A->kc_first, A->nchunks,
-           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap, A->acc);
+           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, A->wcnt, remap, A->acc);
   else
     launch(k_sell_mixed<T, LOGC, false, KC>, g, WAVE, s, A->M, A->nitems, A->items, nwide, A->kc_first, A->nchunks,
-           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, remap, A->acc);
+           A->cs, A->perm, A->scol, (const T*)A->sval, (const T*)x, (T*)y, A->part, A->wcnt, remap, A->acc);
 }
 
 template <typename T, int LOGC, int KC>
@@ -887,7 +929,7 @@ __global__ void k_sell_nslices(int64_t nch, int C, const int64_t* cs, int32_t* n
     const int64_t w = (cs[c + 1] - cs[c]) / C;
     const int64_t n = w <= SELL_KT ? 1 : (w + SELL_KT - 1) / SELL_KT;
     ns[c] = (int32_t)n;
-    wideflag[c] = n > 1;
+    wideflag[c] = n > SELL_FUSE;  // the chunks k_sell_fix finishes
   }
 }
 
@@ -1014,7 +1056,11 @@ spmv_status_t convert_sell(spmv_mat_s* src, spmv_mat_s* A, hipStream_t s) {
     A->nwide = nw[0];
     SPMV_TRY(mat_alloc(A, (void**)&A->items, sizeof(int2) * std::max<int64_t>(A->nitems, 1)));
     SPMV_TRY(mat_alloc(A, (void**)&A->wide, sizeof(int4) * std::max<int64_t>(A->nwide, 1)));
-    if (A->nwide > 0) SPMV_TRY(mat_alloc(A, (void**)&A->part, sizeof(double) * A->nitems * C));
+    if (A->nitems > nch) {  // some chunk has several slices: partial sums and slice counts
+      SPMV_TRY(mat_alloc(A, (void**)&A->part, sizeof(double) * A->nitems * C));
+      SPMV_TRY(mat_alloc(A, (void**)&A->wcnt, sizeof(int32_t) * A->nitems));
+      SPMV_HIP(hipMemsetAsync(A->wcnt, 0, sizeof(int32_t) * A->nitems, s));
+    }
     if (nch) {
       k_sell_items<<<grid_rows(nch), BS, 0, s>>>(nch, ns.as<int32_t>(), ib.as<int32_t>(), wf.as<int32_t>(),
                                                  wp.as<int32_t>(), A->items, A->wide);
