@@ -354,6 +354,35 @@ def test_sell_chunks_wider_than_one_wave_fill(torch):
         assert rowwise_err(Sm.run(device_vec(x64, 0)).cpu().numpy(), yref, den) <= TOL[0], (C, sg)
 
 
+@pytest.mark.parametrize("dt", [0, 1])
+def test_sell_split_chunks_at_the_fold_limit(torch, dt):
+    """Chunks cut into column slices of 64: one of 129 slices (a row of 8,193
+    entries: k_sell_fix adds its slices), one of exactly 128 (8,192 entries)
+    and smaller ones (the last slice item to finish adds them), in one
+    matrix with C = 32 and 64, without and over 2 column bands (the adding
+    path); two runs give identical results (the slice counters are cleared
+    by each run) and meet the bar."""
+    rng = np.random.default_rng(41)
+    M, N = 4000, 60_000
+    lens = rng.integers(0, 9, M)
+    lens[[0, 70, 140, 200, 270]] = [8193, 8192, 4097, 65, 64]  # different chunks for C = 32 and 64
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col = np.concatenate([np.sort(rng.choice(N, n, replace=False)) for n in lens]).astype(np.int32)
+    val = rng.standard_normal(len(col))
+    A = synth.HostCSR(M, N, ptr, col, val)
+    Ad = S.Matrix.from_csr(M, N, ptr, col, val.astype(np.float32) if dt == 1 else val, dt)
+    x64 = synth.vector(N, 6)
+    if dt == 1:
+        x64 = x64.astype(np.float32).astype(np.float64)
+    yref, den = reference(A, x64, dt)
+    for C, nb in [(32, 1), (64, 1), (32, 2)]:
+        Sm = Ad.convert("sell", sell_C=C, sell_sigma=1, bands=nb)
+        y1 = Sm.run(device_vec(x64, dt)).cpu().numpy()
+        y2 = Sm.run(device_vec(x64, dt)).cpu().numpy()
+        assert np.array_equal(y1.view(np.uint8), y2.view(np.uint8)), (C, nb)
+        assert rowwise_err(y1, yref, den) <= TOL[dt], (C, nb)
+
+
 def test_csr_bands_structure(torch):
     """CSR with column bands: band b holds, row by row, the entries whose
     column lies in [b*w, (b+1)*w) with w = ceil(N/8), values bit for bit."""
