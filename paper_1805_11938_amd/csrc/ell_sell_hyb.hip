@@ -483,8 +483,8 @@ __global__ void k_sell_to_csr(int64_t M, int64_t Mpad, int C, const int32_t* per
 // A work item is a slice of at most SELL_KT columns of one chunk, run by C
 // lanes (one per stored row).  Chunks of one slice write y directly; wider
 // chunks write per-slice partial sums.  For a chunk of at most SELL_FUSE
-// slices the item that finishes last (counted with an atomic) adds them in
-// slice order and writes y; longer chunks (rows of more than 8,192 entries)
+// slices the item that finishes last (counted with an atomic) adds them in a
+// fixed order and writes y; longer chunks (rows of more than 8,192 entries)
 // leave that to k_sell_fix, a workgroup per chunk.  The items run in
 // k_sell_mixed, beside the narrow chunks.
 constexpr int SELL_KT = 64;
@@ -621,8 +621,9 @@ __global__ __launch_bounds__(NW * WAVE) void k_sell_kcw(int64_t M, int64_t c0, i
 // last.  Each item stores its partial sums with agent-scope atomic stores
 // (written through to where every XCD reads them), waits until they are
 // done, then counts itself; the item that brings the count to nsl reads the
-// chunk's nsl partial sums of its row with agent-scope atomic loads, in
-// slice order, writes y and clears the count for the next run.  (Fences
+// chunk's nsl partial sums of its row with agent-scope atomic loads and adds
+// them in a fixed order (eight running sums over the slices, combined
+// pairwise), writes y and clears the count for the next run.  (Fences
 // would write back and invalidate a whole XCD's L2 for every item.)  Lanes
 // of one item are C consecutive lanes.
 template <typename T, int LOGC, bool PERM>
